@@ -1,0 +1,226 @@
+/*
+ * stencil.h -- C ABI of the MI355X (gfx950) stencil library.
+ *
+ * The library executes the stencil program that the Open Earth Compiler's two
+ * optimisations produce (arXiv 2005.13014): horizontal diffusion
+ * (Laplacian -> limited fluxes -> update, the hdiffsa benchmark of Sec. VII-B,
+ * Table II) fused with vertical advection (a per-column tridiagonal solve by
+ * the Thomas algorithm, the implicit vertical integration named in
+ * Sec. VII-B).  Stencil inlining (Sec. V-A) becomes one fused kernel that
+ * keeps every temporary on chip; stencil unrolling (Sec. V-A) becomes a
+ * j-unroll factor of the horizontal-diffusion kernel.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All field pointers are DEVICE addresses owned by the caller.  The library
+ *    never frees or reallocates them.
+ *  - Index convention (the paper's range notation, Sec. IV-B): the origin is
+ *    the first interior point; element (i, j, k) of a field lives at
+ *    origin[i + sj * j + sk * k] (element strides, the i stride is 1).
+ *    Interior: 0 <= i < ni, 0 <= j < nj, 0 <= k < nk.  A halo of hi (hj)
+ *    cells on each side in i (j) may be addressed with negative indices or
+ *    indices >= ni (nj).  There is no halo in k.
+ *  - All fields of one call must have the same dtype, the same interior
+ *    extents and the same strides (sj, sk).
+ *  - Only the interior of an output is written; its halo is never touched.
+ *  - Outputs must not overlap any input or other output (stencil programs are
+ *    alias-free, Sec. IV-E); overlap of the addressed byte ranges is rejected.
+ *  - Input halos must be at least the access extent that shape inference
+ *    derives for the call (Sec. V-B); otherwise STENCIL_E_HALO.
+ *  - Calls validate on the host, then enqueue asynchronously on the given HIP
+ *    stream (a hipStream_t passed as void*; NULL = the null stream) and never
+ *    synchronise.  Validation errors return before anything is enqueued.
+ *  - Empty interiors (ni, nj or nk == 0) are valid no-ops.
+ *  - Every element offset must fit in a signed 32-bit integer.
+ *  - Return value: STENCIL_OK or an error code; stencil_last_error() gives a
+ *    message for the calling thread's last error.
+ */
+#ifndef STENCIL_H
+#define STENCIL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STENCIL_ABI_VERSION 1
+
+typedef enum {
+    STENCIL_F64 = 0,  /* storage and arithmetic in double */
+    STENCIL_F32 = 1,  /* storage and stencil arithmetic in float; the Thomas
+                         elimination and back-substitution in double */
+    STENCIL_BF16 = 2  /* bfloat16 storage (raw uint16 bit patterns), float
+                         stencil arithmetic, double Thomas solve; stores round
+                         to nearest even */
+} stencil_dtype;
+
+typedef enum {
+    STENCIL_OK = 0,
+    STENCIL_E_NULL = 1,        /* a required pointer is NULL */
+    STENCIL_E_DTYPE = 2,       /* unknown dtype, or dtypes differ within a call */
+    STENCIL_E_SHAPE = 3,       /* negative extents, or extents differ within a call */
+    STENCIL_E_STRIDE = 4,      /* strides cannot hold extents + halo, or differ within a call */
+    STENCIL_E_HALO = 5,        /* an input halo is narrower than the access extent */
+    STENCIL_E_ALIAS = 6,       /* an output overlaps an input or another output */
+    STENCIL_E_UNSUPPORTED = 7, /* size or option the library does not implement */
+    STENCIL_E_HIP = 8,         /* HIP runtime or launch error */
+    STENCIL_E_ARG = 9          /* invalid scalar argument or configuration */
+} stencil_status;
+
+/* A halo-padded 3D field (the paper's !stencil.field with its asserted range,
+ * Sec. IV-A).  `origin` is the device address of interior element (0,0,0). */
+typedef struct {
+    void *origin;
+    int32_t dtype;       /* stencil_dtype */
+    int32_t ni, nj, nk;  /* interior extents */
+    int32_t hi, hj;      /* halo cells available on each side in i and j */
+    int64_t sj, sk;      /* element strides of j and k; sj >= ni + 2 hi,
+                            sk >= sj * (nj + 2 hj) */
+} stencil_field_t;
+
+/* Optimisation level, the levels compared in Sec. VII-C. */
+typedef enum {
+    STENCIL_LEVEL_DEFAULT = 0,  /* the library's choice (fused) */
+    STENCIL_LEVEL_ORIGINAL = 1, /* one kernel per stencil operator; every
+                                   temporary (lap, fluxes, h, rhs, Thomas
+                                   coefficients) goes through device memory */
+    STENCIL_LEVEL_INLINE = 2    /* all operators fused into one kernel;
+                                   temporaries stay on chip */
+} stencil_level;
+
+/* Optional tuning knobs; pass NULL for defaults.  Zero fields mean default. */
+typedef struct {
+    int32_t level;    /* stencil_level */
+    int32_t unroll;   /* j-unroll factor of stencil_hdiff: 1, 2 or 4 (Sec. V-A) */
+    int32_t tile_j;   /* rows of columns per workgroup: 1, 2 or 4 (fused kernels) */
+    int32_t prefetch; /* k-levels loaded ahead of use: 2, 4 or 8 */
+} stencil_config_t;
+
+/* Horizontal diffusion, per level k and interior point (i, j):
+ *   lap = 4u - u(i+1) - u(i-1) - u(j+1) - u(j-1)
+ *   flx = lap(i+1) - lap(i), set to 0 when flx * (u(i+1) - u(i)) > 0
+ *   fly = lap(j+1) - lap(j), set to 0 when fly * (u(j+1) - u(j)) > 0
+ *   out = u - coeff * (flx - flx(i-1) + fly - fly(j-1))
+ * The paper names this benchmark (Sec. VII-B, Table II: four stencil
+ * operators, a min-style limiter) without printing its formula; the limiter is
+ * branch-free control flow inside the operator (Sec. IV-F).
+ * Inputs: u (halo >= 2 in i and j), coeff (interior read only).
+ * Output: out (interior written).  cfg: level, unroll. */
+int stencil_hdiff(const stencil_field_t *u, const stencil_field_t *coeff,
+                  const stencil_field_t *out, const stencil_config_t *cfg, void *stream);
+
+/* Vertical advection of h, per column (i, j):
+ *   F(k+1/2) = (w(k) + w(k+1))/2 * (h(k) + h(k+1))/2,  F(-1/2) = F(nk-1/2) = 0
+ *   d(k)     = h(k) - dt * (F(k+1/2) - F(k-1/2))
+ *   a(k) x(k-1) + b(k) x(k) + c(k) x(k+1) = d(k)   (a(0), c(nk-1) ignored)
+ * solved by Thomas forward elimination and back-substitution in double
+ * precision whatever the storage dtype (Sec. VII-B names the Thomas algorithm
+ * for implicit vertical integration).  All inputs are read on the interior
+ * only; the system must be non-singular (e.g. diagonally dominant).
+ * Inputs: h, wcon, a, b, c.  Output: x.  Scalar: dt (finite). */
+int stencil_vadv(const stencil_field_t *h, const stencil_field_t *wcon,
+                 const stencil_field_t *a, const stencil_field_t *b,
+                 const stencil_field_t *c, double dt, const stencil_field_t *x,
+                 const stencil_config_t *cfg, void *stream);
+
+/* The fused program x = vadv(hdiff(u, coeff), wcon, a, b, c, dt): stencil
+ * inlining (Sec. V-A) of the two stages.  With level ORIGINAL it runs one
+ * kernel per operator through library-owned device scratch instead.
+ * Inputs: u (halo >= 2), coeff, wcon, a, b, c (interior read only).
+ * Output: x.  cfg: level, tile_j, prefetch. */
+int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field_t *coeff,
+                       const stencil_field_t *wcon, const stencil_field_t *a,
+                       const stencil_field_t *b, const stencil_field_t *c, double dt,
+                       const stencil_field_t *x, const stencil_config_t *cfg, void *stream);
+
+/* Reverse mode of stencil_hdiff_vadv for the loss L = sum over the interior
+ * of w * x.  With the limiter decisions of the forward pass frozen (their
+ * derivative is taken as zero):
+ *   lam = T^-T w              (transposed Thomas solve, double)
+ *   Fhat(k+1/2) = -dt (lam(k) - lam(k+1))
+ *   gh(k) = lam(k) + sum over faces f of k of Fhat(f) * wbar(f) / 2
+ *   gwcon(k) = sum over faces f of k of Fhat(f) * hbar(f) / 2
+ *   gcoeff = -gh * (flx - flx(i-1) + fly - fly(j-1))
+ *   gu = gh + masked transposed flux and Laplacian stencils applied to gh
+ * Inputs: u (halo >= 2), coeff, wcon, a, b, c, w (interior read only).
+ * Outputs: gu (needs halo >= 2: its interior and 2-cell ring are
+ * overwritten; the four 3-cell corner notches of the ring receive 0),
+ * gcoeff and gwcon (interior).  Uses library-owned device scratch. */
+int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stencil_field_t *coeff,
+                               const stencil_field_t *wcon, const stencil_field_t *a,
+                               const stencil_field_t *b, const stencil_field_t *c, double dt,
+                               const stencil_field_t *w, const stencil_field_t *gu,
+                               const stencil_field_t *gcoeff, const stencil_field_t *gwcon,
+                               const stencil_config_t *cfg, void *stream);
+
+/* ---- batched timestep program ------------------------------------------ */
+
+/* Stages of a timestep program, applied in this order to every field. */
+enum {
+    STENCIL_STAGE_HDIFF = 1,
+    STENCIL_STAGE_VADV = 2,
+    STENCIL_STAGE_VDIFF = 4,  /* y(k) = x(k) + kappa (x(k+1) - 2x(k) + x(k-1)),
+                                 zero flux through the bottom and top faces */
+    STENCIL_STAGE_HGRAD = 8   /* z = y - beta_h ((y(i+1)-y(i-1))/2 + (y(j+1)-y(j-1))/2)
+                                 - beta_v Dk y, Dk centred inside the column and
+                                 one-sided at its two ends */
+};
+
+/* One subdomain: nfields prognostic fields sharing coeff, wcon, a, b, c. */
+typedef struct {
+    stencil_field_t coeff, wcon, a, b, c;
+    int32_t nfields;
+    const stencil_field_t *u;  /* nfields inputs */
+    const stencil_field_t *z;  /* nfields outputs */
+} stencil_subdomain_t;
+
+/* A timestep program over independent subdomains of different sizes
+ * (a stencil program with eager program-level control, Sec. IV-F).
+ * stages: HDIFF|VADV, HDIFF|VADV|VDIFF or HDIFF|VADV|VDIFF|HGRAD.
+ * Shape inference (Sec. V-B) derives the halos: with HGRAD the earlier stages
+ * run on the interior grown by one cell, so u needs halo >= 3 and the shared
+ * coefficient fields halo >= 1; otherwise u needs 2 and the coefficients 0. */
+typedef struct {
+    int32_t nsub;
+    const stencil_subdomain_t *sub;
+    int32_t stages;
+    int32_t flags;  /* STENCIL_PROGRAM_* */
+    double dt, kappa, beta_h, beta_v;
+} stencil_program_t;
+
+enum {
+    STENCIL_PROGRAM_GRAPH = 1,    /* capture the launches in a hipGraph cached on
+                                     the program signature and replay it */
+    STENCIL_PROGRAM_AUTOTUNE = 2  /* time the candidate kernel configurations on
+                                     first use (synchronises the stream once) */
+};
+
+/* Runs the program.  All fields of one subdomain share dtype, extents and
+ * strides; subdomains may differ in size and layout.  Output z of each field
+ * is written on its interior.  Uses library-owned device scratch. */
+int stencil_program_run(const stencil_program_t *prog, void *stream);
+
+/* ---- library management and measurement --------------------------------- */
+
+/* Message describing the calling thread's last nonzero return code. */
+const char *stencil_last_error(void);
+
+/* STENCIL_ABI_VERSION of the loaded library. */
+int stencil_abi_version(void);
+
+/* Releases all library-owned device memory and cached graphs.  The library
+ * stays usable; resources are re-created on demand.  Must not race with
+ * calls in flight on other threads. */
+void stencil_shutdown(void);
+
+/* Bandwidth probe: copies nbytes (a multiple of 16, both pointers 16-byte
+ * aligned) from src to dst with a plain streaming kernel.  Measures the
+ * achievable HBM copy rate that the stencil kernels are compared against. */
+int stencil_probe_copy(const void *src, void *dst, int64_t nbytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STENCIL_H */

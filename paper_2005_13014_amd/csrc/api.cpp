@@ -1,0 +1,374 @@
+// C ABI of the stencil library: host-side validation and dispatch.
+//
+// Every entry point validates its descriptors on the host before anything is
+// enqueued (the checks a stencil program's asserted ranges and shape inference
+// imply, Sec. IV-E and V-B), then launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/stencil.h"
+#include "launch.hpp"
+#include "program.hpp"
+
+#define STENCIL_API extern "C" __attribute__((visibility("default")))
+
+namespace stl {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(STENCIL_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Library-owned device scratch, one buffer per (device, stream) so that calls
+// on different streams never share temporaries.
+// ---------------------------------------------------------------------------
+namespace {
+struct Scratch {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_scratch_mu;
+std::map<std::pair<int, hipStream_t>, Scratch> g_scratch;
+}  // namespace
+
+int scratch_get(hipStream_t st, size_t bytes, void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    Scratch &s = g_scratch[{dev, st}];
+    if (s.bytes < bytes) {
+        if (s.p) {
+            // Kernels enqueued earlier on this stream may still use the old buffer.
+            e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            hipFree(s.p);
+            s.p = nullptr;
+            s.bytes = 0;
+        }
+        e = hipMalloc(&s.p, bytes);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(scratch)");
+        s.bytes = bytes;
+    }
+    *out = s.p;
+    return STENCIL_OK;
+}
+
+void scratch_release_all() {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch.empty()) hipDeviceSynchronize();
+    for (auto &kv : g_scratch)
+        if (kv.second.p) hipFree(kv.second.p);
+    g_scratch.clear();
+}
+
+// ---------------------------------------------------------------------------
+// Descriptor validation
+// ---------------------------------------------------------------------------
+size_t elem_size(int dtype) {
+    return dtype == STENCIL_F64 ? 8 : dtype == STENCIL_F32 ? 4 : 2;
+}
+
+bool empty(const stencil_field_t *f) { return f->ni == 0 || f->nj == 0 || f->nk == 0; }
+
+// Element offsets (relative to origin) of the first and last addressable cell.
+static void extent(const stencil_field_t *f, long long *lo, long long *hi) {
+    *lo = -static_cast<long long>(f->hi) - static_cast<long long>(f->hj) * f->sj;
+    *hi = static_cast<long long>(f->ni + f->hi - 1) + static_cast<long long>(f->nj + f->hj - 1) * f->sj +
+          static_cast<long long>(f->nk - 1) * f->sk;
+}
+
+int check_field(const stencil_field_t *f, const char *name) {
+    if (!f) return fail(STENCIL_E_NULL, "%s: descriptor is NULL", name);
+    if (f->dtype != STENCIL_F64 && f->dtype != STENCIL_F32 && f->dtype != STENCIL_BF16)
+        return fail(STENCIL_E_DTYPE, "%s: unknown dtype %d", name, f->dtype);
+    if (f->ni < 0 || f->nj < 0 || f->nk < 0)
+        return fail(STENCIL_E_SHAPE, "%s: negative extent (%d, %d, %d)", name, f->ni, f->nj, f->nk);
+    if (f->hi < 0 || f->hj < 0) return fail(STENCIL_E_HALO, "%s: negative halo", name);
+    if (empty(f)) return STENCIL_OK;
+    if (!f->origin) return fail(STENCIL_E_NULL, "%s: origin is NULL", name);
+    if (f->sj < static_cast<long long>(f->ni) + 2 * f->hi)
+        return fail(STENCIL_E_STRIDE, "%s: sj=%lld < ni + 2 hi = %d", name, (long long)f->sj,
+                    f->ni + 2 * f->hi);
+    if (f->nk > 1 && f->sk < f->sj * (static_cast<long long>(f->nj) + 2 * f->hj))
+        return fail(STENCIL_E_STRIDE, "%s: sk=%lld < sj (nj + 2 hj)", name, (long long)f->sk);
+    long long lo, hi;
+    extent(f, &lo, &hi);
+    if (lo < -2147483647LL || hi > 2147483647LL)
+        return fail(STENCIL_E_UNSUPPORTED, "%s: element offsets exceed 32 bits", name);
+    return STENCIL_OK;
+}
+
+// All fields share dtype, interior extents and strides.
+int check_same(const stencil_field_t *const *fs, const char *const *names, int n) {
+    const stencil_field_t *r = fs[0];
+    for (int q = 1; q < n; ++q) {
+        const stencil_field_t *f = fs[q];
+        if (f->dtype != r->dtype)
+            return fail(STENCIL_E_DTYPE, "%s has dtype %d but %s has %d", names[q], f->dtype,
+                        names[0], r->dtype);
+        if (f->ni != r->ni || f->nj != r->nj || f->nk != r->nk)
+            return fail(STENCIL_E_SHAPE, "%s extents (%d,%d,%d) differ from %s (%d,%d,%d)", names[q],
+                        f->ni, f->nj, f->nk, names[0], r->ni, r->nj, r->nk);
+        if (!empty(f) && (f->sj != r->sj || (f->nk > 1 && f->sk != r->sk)))
+            return fail(STENCIL_E_STRIDE, "%s strides differ from %s", names[q], names[0]);
+    }
+    return STENCIL_OK;
+}
+
+int check_halo(const stencil_field_t *f, const char *name, int need) {
+    if (f->hi < need || f->hj < need)
+        return fail(STENCIL_E_HALO, "%s: halo (%d, %d) narrower than the access extent %d", name,
+                    f->hi, f->hj, need);
+    return STENCIL_OK;
+}
+
+// Byte ranges of outputs must not overlap any other field of the call.
+int check_alias(const stencil_field_t *const *fs, const char *const *names, int n, int nout) {
+    struct R {
+        uintptr_t lo, hi;
+    };
+    std::vector<R> r(n);
+    for (int q = 0; q < n; ++q) {
+        long long lo, hi;
+        extent(fs[q], &lo, &hi);
+        const size_t es = elem_size(fs[q]->dtype);
+        const uintptr_t base = reinterpret_cast<uintptr_t>(fs[q]->origin);
+        r[q] = {base + static_cast<intptr_t>(lo * static_cast<long long>(es)),
+                base + static_cast<intptr_t>((hi + 1) * static_cast<long long>(es))};
+    }
+    for (int o = n - nout; o < n; ++o)
+        for (int q = 0; q < n; ++q) {
+            if (q == o) continue;
+            if (r[o].lo < r[q].hi && r[q].lo < r[o].hi)
+                return fail(STENCIL_E_ALIAS, "output %s overlaps %s", names[o], names[q]);
+        }
+    return STENCIL_OK;
+}
+
+#define TRY(x)                            \
+    do {                                  \
+        int rc_ = (x);                    \
+        if (rc_ != STENCIL_OK) return rc_; \
+    } while (0)
+
+int check_call(const stencil_field_t *const *fs, const char *const *names, int n, int nout) {
+    for (int q = 0; q < n; ++q) TRY(check_field(fs[q], names[q]));
+    TRY(check_same(fs, names, n));
+    bool any_empty = false;
+    for (int q = 0; q < n; ++q) any_empty |= empty(fs[q]);
+    if (!any_empty) TRY(check_alias(fs, names, n, nout));
+    return STENCIL_OK;
+}
+
+static stencil_config_t config_or_default(const stencil_config_t *cfg) {
+    stencil_config_t c{};
+    if (cfg) c = *cfg;
+    return c;
+}
+
+static int launch_status(hipError_t e, const char *what) {
+    if (e != hipSuccess) return hip_fail(e, what);
+    return STENCIL_OK;
+}
+
+// Plain-path launch limits (grid y and z).
+static int check_plain_dims(int I, int J, int K) {
+    if (K > 65535 || (J + 5) / 4 > 65535 || (I + 2) / 64 + 1 > 2147483647)
+        return fail(STENCIL_E_UNSUPPORTED, "extents too large for the unfused kernels");
+    (void)I;
+    return STENCIL_OK;
+}
+
+static int run_plain(int dtype, PlainArgs a, hipStream_t st) {
+    TRY(check_plain_dims(a.I, a.J, a.K));
+    void *scratch = nullptr;
+    TRY(scratch_get(st, plain_scratch_bytes(dtype, a.I, a.J, a.K, a.vadv), &scratch));
+    a.scratch = scratch;
+    return launch_status(launch_plain(dtype, a, st), "unfused kernels");
+}
+
+static hipError_t launch_fused(int dtype, const VadvArgs &a, int tj, int pf, hipStream_t st) {
+    switch (dtype) {
+    case STENCIL_F64: return launch_fused_f64(a, tj, pf, st);
+    case STENCIL_F32: return launch_fused_f32(a, tj, pf, st);
+    default: return launch_fused_bf16(a, tj, pf, st);
+    }
+}
+
+static hipError_t launch_vadv_any(int dtype, const VadvArgs &a, hipStream_t st) {
+    switch (dtype) {
+    case STENCIL_F64: return launch_vadv_f64(a, st);
+    case STENCIL_F32: return launch_vadv_f32(a, st);
+    default: return launch_vadv_bf16(a, st);
+    }
+}
+
+int kmax_column(int dtype) { return dtype == STENCIL_F64 ? KMAX_COLUMN_F64 : KMAX_COLUMN_F32; }
+
+}  // namespace stl
+
+using namespace stl;
+
+// ---------------------------------------------------------------------------
+// Entry points
+// ---------------------------------------------------------------------------
+STENCIL_API int stencil_abi_version(void) { return STENCIL_ABI_VERSION; }
+
+STENCIL_API const char *stencil_last_error(void) { return g_last_error.c_str(); }
+
+STENCIL_API void stencil_shutdown(void) {
+    program_release_all();
+    scratch_release_all();
+}
+
+STENCIL_API int stencil_hdiff(const stencil_field_t *u, const stencil_field_t *coeff,
+                              const stencil_field_t *out, const stencil_config_t *cfg,
+                              void *stream) {
+    const stencil_field_t *fs[] = {u, coeff, out};
+    const char *names[] = {"u", "coeff", "out"};
+    TRY(check_call(fs, names, 3, 1));
+    TRY(check_halo(u, "u", 2));
+    const stencil_config_t c = config_or_default(cfg);
+    if (c.level < 0 || c.level > STENCIL_LEVEL_INLINE)
+        return fail(STENCIL_E_ARG, "unknown level %d", c.level);
+    const int unroll = c.unroll ? c.unroll : 1;
+    if (unroll != 1 && unroll != 2 && unroll != 4)
+        return fail(STENCIL_E_ARG, "unroll must be 1, 2 or 4 (got %d)", c.unroll);
+    if (empty(u)) return STENCIL_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (c.level == STENCIL_LEVEL_ORIGINAL) {
+        PlainArgs a{};
+        a.u = u->origin;
+        a.coeff = coeff->origin;
+        a.x = out->origin;
+        a.I = u->ni; a.J = u->nj; a.K = u->nk;
+        a.sj = static_cast<int>(u->sj); a.sk = static_cast<int>(u->sk);
+        a.vadv = false;
+        return run_plain(u->dtype, a, st);
+    }
+    HdiffArgs a{};
+    a.u = u->origin;
+    a.coeff = coeff->origin;
+    a.out = out->origin;
+    a.I = u->ni; a.J = u->nj; a.K = u->nk;
+    a.sj = static_cast<int>(u->sj); a.sk = static_cast<int>(u->sk);
+    return launch_status(launch_hdiff(u->dtype, a, unroll, st), "hdiff kernel");
+}
+
+static int check_dt(double dt) {
+    if (!std::isfinite(dt)) return fail(STENCIL_E_ARG, "dt must be finite");
+    return STENCIL_OK;
+}
+
+STENCIL_API int stencil_vadv(const stencil_field_t *h, const stencil_field_t *wcon,
+                             const stencil_field_t *a, const stencil_field_t *b,
+                             const stencil_field_t *c, double dt, const stencil_field_t *x,
+                             const stencil_config_t *cfg, void *stream) {
+    const stencil_field_t *fs[] = {h, wcon, a, b, c, x};
+    const char *names[] = {"h", "wcon", "a", "b", "c", "x"};
+    TRY(check_call(fs, names, 6, 1));
+    TRY(check_dt(dt));
+    const stencil_config_t cf = config_or_default(cfg);
+    if (cf.level < 0 || cf.level > STENCIL_LEVEL_INLINE)
+        return fail(STENCIL_E_ARG, "unknown level %d", cf.level);
+    if (empty(h)) return STENCIL_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int dtype = h->dtype;
+    if (cf.level == STENCIL_LEVEL_ORIGINAL || h->nk > kmax_column(dtype)) {
+        PlainArgs p{};
+        p.h = h->origin; p.wcon = wcon->origin; p.a = a->origin; p.b = b->origin; p.c = c->origin;
+        p.x = x->origin;
+        p.I = h->ni; p.J = h->nj; p.K = h->nk;
+        p.sj = static_cast<int>(h->sj); p.sk = static_cast<int>(h->sk);
+        p.dt = dt;
+        p.vadv = true;
+        return run_plain(dtype, p, st);
+    }
+    VadvArgs v{};
+    v.u = h->origin; v.wcon = wcon->origin; v.a = a->origin; v.b = b->origin; v.c = c->origin;
+    v.x = x->origin;
+    v.I = h->ni; v.J = h->nj; v.K = h->nk;
+    v.sj = static_cast<int>(h->sj); v.sk = static_cast<int>(h->sk);
+    v.dt = dt;
+    return launch_status(launch_vadv_any(dtype, v, st), "vadv kernel");
+}
+
+STENCIL_API int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field_t *coeff,
+                                   const stencil_field_t *wcon, const stencil_field_t *a,
+                                   const stencil_field_t *b, const stencil_field_t *c, double dt,
+                                   const stencil_field_t *x, const stencil_config_t *cfg,
+                                   void *stream) {
+    const stencil_field_t *fs[] = {u, coeff, wcon, a, b, c, x};
+    const char *names[] = {"u", "coeff", "wcon", "a", "b", "c", "x"};
+    TRY(check_call(fs, names, 7, 1));
+    TRY(check_halo(u, "u", 2));
+    TRY(check_dt(dt));
+    const stencil_config_t cf = config_or_default(cfg);
+    if (cf.level < 0 || cf.level > STENCIL_LEVEL_INLINE)
+        return fail(STENCIL_E_ARG, "unknown level %d", cf.level);
+    const int dtype = u->dtype;
+    int tj = cf.tile_j ? cf.tile_j : 4;
+    int pf = cf.prefetch ? cf.prefetch : (dtype == STENCIL_F64 ? 2 : 4);
+    if (cf.level != STENCIL_LEVEL_ORIGINAL && !fused_variant_compiled(dtype, tj, pf))
+        return fail(STENCIL_E_UNSUPPORTED, "no compiled fused variant tile_j=%d prefetch=%d", tj, pf);
+    if (empty(u)) return STENCIL_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (cf.level == STENCIL_LEVEL_ORIGINAL || u->nk > kmax_column(dtype)) {
+        if (cf.level == STENCIL_LEVEL_INLINE)
+            return fail(STENCIL_E_UNSUPPORTED, "fused kernel supports nk <= %d for this dtype",
+                        kmax_column(dtype));
+        PlainArgs p{};
+        p.u = u->origin; p.coeff = coeff->origin;
+        p.wcon = wcon->origin; p.a = a->origin; p.b = b->origin; p.c = c->origin;
+        p.x = x->origin;
+        p.I = u->ni; p.J = u->nj; p.K = u->nk;
+        p.sj = static_cast<int>(u->sj); p.sk = static_cast<int>(u->sk);
+        p.dt = dt;
+        p.vadv = true;
+        return run_plain(dtype, p, st);
+    }
+    VadvArgs v{};
+    v.u = u->origin; v.coeff = coeff->origin;
+    v.wcon = wcon->origin; v.a = a->origin; v.b = b->origin; v.c = c->origin;
+    v.x = x->origin;
+    v.I = u->ni; v.J = u->nj; v.K = u->nk;
+    v.sj = static_cast<int>(u->sj); v.sk = static_cast<int>(u->sk);
+    v.dt = dt;
+    return launch_status(launch_fused(dtype, v, tj, pf, st), "fused hdiff+vadv kernel");
+}
+
+STENCIL_API int stencil_probe_copy(const void *src, void *dst, int64_t nbytes, void *stream) {
+    if (!src || !dst) return fail(STENCIL_E_NULL, "probe_copy: NULL pointer");
+    if (nbytes < 0 || nbytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 ||
+        reinterpret_cast<uintptr_t>(dst) % 16)
+        return fail(STENCIL_E_ARG, "probe_copy: nbytes and pointers must be 16-byte aligned");
+    const uintptr_t s = reinterpret_cast<uintptr_t>(src), d = reinterpret_cast<uintptr_t>(dst);
+    if (s < d + nbytes && d < s + nbytes) return fail(STENCIL_E_ALIAS, "probe_copy: ranges overlap");
+    return launch_status(launch_probe_copy(src, dst, nbytes, static_cast<hipStream_t>(stream)),
+                         "copy kernel");
+}

@@ -1,0 +1,121 @@
+// Device-side building blocks shared by the stencil kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stl {
+
+// ---------------------------------------------------------------------------
+// Storage types.  A field is stored as double, float or bfloat16 (raw bits);
+// the stencil arithmetic runs in the compute type C of the storage type and
+// the Thomas solve always in double.
+// ---------------------------------------------------------------------------
+template <class T> struct Storage;
+
+template <> struct Storage<double> {
+    using C = double;
+    static __device__ __forceinline__ double load(const double *p) { return *p; }
+    static __device__ __forceinline__ void store(double *p, double v) { *p = v; }
+    static __device__ __forceinline__ void store_d(double *p, double v) { *p = v; }
+};
+
+template <> struct Storage<float> {
+    using C = float;
+    static __device__ __forceinline__ float load(const float *p) { return *p; }
+    static __device__ __forceinline__ void store(float *p, float v) { *p = v; }
+    static __device__ __forceinline__ void store_d(float *p, double v) { *p = static_cast<float>(v); }
+};
+
+// bfloat16: the upper half of an IEEE float.  Loads are exact; stores round
+// to nearest, ties to even (NaN stays NaN).
+template <> struct Storage<uint16_t> {
+    using C = float;
+    static __device__ __forceinline__ float load(const uint16_t *p) {
+        return __uint_as_float(static_cast<uint32_t>(*p) << 16);
+    }
+    static __device__ __forceinline__ uint16_t round(float v) {
+        uint32_t bits = __float_as_uint(v);
+        if ((bits & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((bits >> 16) | 0x40u);
+        bits += 0x7fffu + ((bits >> 16) & 1u);
+        return static_cast<uint16_t>(bits >> 16);
+    }
+    static __device__ __forceinline__ void store(uint16_t *p, float v) { *p = round(v); }
+    // A double rounded once to bfloat16: first to float with round-to-odd
+    // (truncate, then set the last bit if anything was cut off), which keeps
+    // the second rounding to nearest-even correct because float carries more
+    // than two extra bits.
+    static __device__ __forceinline__ void store_d(uint16_t *p, double v) {
+        float f = static_cast<float>(v);
+        // static_cast rounds to nearest; step back toward zero if it rounded up.
+        if (fabs(static_cast<double>(f)) > fabs(v)) f = nextafterf(f, 0.0f);
+        uint32_t bits = __float_as_uint(f);
+        if (static_cast<double>(f) != v) bits |= 1u;
+        *p = round(__uint_as_float(bits));
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Workgroup -> tile map aware of the 8 XCDs of MI355X.  Consecutive
+// workgroup ids are dispatched round-robin over the XCDs, each of which has a
+// private L2; this bijection hands each XCD a contiguous range of tiles, so
+// tiles that share halo rows are resident in the same L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int full = nb >> 3, rem = nb & 7;
+    const int x = b & 7, q = b >> 3;
+    return x * full + min(x, rem) + q;
+}
+
+// ---------------------------------------------------------------------------
+// The horizontal-diffusion operator for one point, from a staged tile of u.
+// `t` points at the centre value; `pitch` is the tile's row length.  The
+// Laplacian is recomputed at the centre and its four neighbours (inlining,
+// redundant computation instead of stored temporaries), the four fluxes are
+// limited with a select, and the update is returned.  The order of the
+// floating-point operations follows the operator definitions.
+// ---------------------------------------------------------------------------
+template <class C, int PITCH>
+__device__ __forceinline__ C hdiff_point(const C *t, C cf) {
+    const C uc = t[0], ue = t[1], uw = t[-1], un = t[PITCH], us = t[-PITCH];
+    const C uee = t[2], uww = t[-2], unn = t[2 * PITCH], uss = t[-2 * PITCH];
+    const C une = t[PITCH + 1], unw = t[PITCH - 1], use = t[-PITCH + 1], usw = t[-PITCH - 1];
+    const C four = C(4);
+    const C lc = four * uc - ue - uw - un - us;
+    const C le = four * ue - uee - uc - une - use;
+    const C lw = four * uw - uc - uww - unw - usw;
+    const C ln = four * un - une - unw - unn - uc;
+    const C ls = four * us - use - usw - uc - uss;
+    C fe = le - lc;
+    C fw = lc - lw;
+    C fn = ln - lc;
+    C fs = lc - ls;
+    fe = (fe * (ue - uc) > C(0)) ? C(0) : fe;
+    fw = (fw * (uc - uw) > C(0)) ? C(0) : fw;
+    fn = (fn * (un - uc) > C(0)) ? C(0) : fn;
+    fs = (fs * (uc - us) > C(0)) ? C(0) : fs;
+    return uc - cf * (fe - fw + fn - fs);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel arguments.  All fields of one call share the strides (sj, sk); each
+// pointer is the field's interior origin.
+// ---------------------------------------------------------------------------
+struct HdiffArgs {
+    const void *u, *coeff;
+    void *out;
+    int I, J, K, sj, sk;
+    int nbi, nbj;  // tiles in i and j
+};
+
+struct VadvArgs {
+    const void *u;      // u (fused: hdiff input) or h (vadv alone)
+    const void *coeff;  // fused only
+    const void *wcon, *a, *b, *c;
+    void *x;
+    int I, J, K, sj, sk;
+    int nbi, nbj;
+    double dt;
+};
+
+}  // namespace stl

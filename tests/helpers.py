@@ -1,0 +1,48 @@
+"""Shared test helpers: error measures, tolerances and field construction.
+
+Errors are normwise (the paper checks outputs against naive versions with a
+relative error bound, Sec. VII-A; pointwise relative error is undefined near
+zero): max|x - ref| / max|ref| and RMS(x - ref) / RMS(ref)."""
+import numpy as np
+
+DT = 10.0
+SEED = 200513014
+
+# Normwise tolerances: FP64 must agree with the FP64 oracle to 1e-12; FP32
+# storage/arithmetic (with FP64 Thomas) to 1e-5; bfloat16 storage carries its
+# own output rounding of up to 2^-8 relative, plus the FP32 arithmetic.
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2.0 ** -8 + 1e-5}
+
+
+def normwise(x, ref):
+    den = np.abs(ref).max() if ref.size else 1.0
+    return float(np.abs(x - ref).max() / den) if x.size else 0.0
+
+
+def rms_rel(x, ref):
+    if not x.size:
+        return 0.0
+    return float(np.sqrt(np.mean((x - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))
+
+
+def interior(a, h):
+    return a if h == 0 else a[:, h:-h, h:-h]
+
+
+def gpu_fields(f, halo, dtype, names):
+    """Device fields (binding.Field) holding the padded arrays f[name]."""
+    from paper_2005_13014_amd import binding as B
+    return {n: B.Field.from_numpy(f[n], halo, dtype) for n in names}
+
+
+def out_field(ni, nj, nk, halo, dtype, canary=-7.0):
+    """An output field whose halo (and interior) start at a canary value."""
+    from paper_2005_13014_amd import binding as B
+    return B.Field.empty(ni, nj, nk, halo, dtype, fill=canary)
+
+
+def halo_untouched(field, canary=-7.0):
+    p = field.to_numpy()
+    mask = np.ones(p.shape, bool)
+    mask[:, field.hj:field.hj + field.nj, field.hi:field.hi + field.ni] = False
+    return bool(np.all(p[mask] == canary))

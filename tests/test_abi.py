@@ -1,0 +1,169 @@
+"""The C ABI on the CPU: the library loads, exports exactly what the header
+declares, and rejects invalid calls on the host with the documented codes
+before anything touches a GPU (no compute call is made here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stencil.h")
+
+B = pytest.importorskip("paper_2005_13014_amd.binding")
+
+if not os.path.exists(B.LIB_PATH):
+    pytest.skip("libstencil.so not built", allow_module_level=True)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(stencil_\w+)\s*\(", text,
+                                 re.M)))
+
+
+def test_header_declarations_are_exported():
+    decl = declared_functions()
+    assert len(decl) >= 9
+    lib = B.lib()
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert sorted(B.EXPORTS) == decl
+
+
+def test_only_the_abi_is_exported():
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    text_syms = sorted(l.split()[-1] for l in out.splitlines() if " T " in l)
+    assert text_syms == declared_functions()
+
+
+def test_abi_version_matches_header():
+    m = re.search(r"#define STENCIL_ABI_VERSION (\d+)", open(HEADER).read())
+    assert B.stencil_abi_version() == int(m.group(1))
+
+
+# ---- validation (host only) ------------------------------------------------
+
+FAKE = 1 << 40          # never dereferenced: validation fails before any launch
+
+
+def fd(origin=FAKE, dtype=1, ni=16, nj=12, nk=5, hi=2, hj=2, sj=None, sk=None):
+    sj = ni + 2 * hi if sj is None else sj
+    sk = sj * (nj + 2 * hj) if sk is None else sk
+    return B.FieldDesc(origin, dtype, ni, nj, nk, hi, hj, sj, sk)
+
+
+def spaced(n, **kw):
+    """n descriptors with disjoint byte ranges."""
+    out = []
+    for q in range(n):
+        out.append(fd(origin=FAKE + q * (1 << 30), **kw))
+    return out
+
+
+def hdiff(u, coeff, out, cfg=None):
+    r = ctypes.byref
+    return B.lib().stencil_hdiff(r(u) if u else None, r(coeff) if coeff else None,
+                                 r(out) if out else None, r(cfg) if cfg else None, None)
+
+
+def fused(fs, dt=10.0, cfg=None):
+    r = ctypes.byref
+    return B.lib().stencil_hdiff_vadv(*[r(f) for f in fs[:6]], dt, r(fs[6]),
+                                      r(cfg) if cfg else None, None)
+
+
+def vadv(fs, dt=10.0):
+    r = ctypes.byref
+    return B.lib().stencil_vadv(*[r(f) for f in fs[:5]], dt, r(fs[5]), None, None)
+
+
+def test_null_descriptor_and_origin():
+    u, c, o = spaced(3)
+    assert hdiff(None, c, o) == 1
+    assert "NULL" in B.stencil_last_error()
+    u.origin = None
+    assert hdiff(u, c, o) == 1
+
+
+def test_dtype_checks():
+    u, c, o = spaced(3)
+    c.dtype = 0
+    assert hdiff(u, c, o) == 2
+    u, c, o = spaced(3, dtype=7)
+    assert hdiff(u, c, o) == 2
+
+
+def test_shape_checks():
+    u, c, o = spaced(3)
+    o.nj = 11
+    o.sk = o.sj * (11 + 4)
+    assert hdiff(u, c, o) == 3
+    u, c, o = spaced(3)
+    u.ni = -1
+    assert hdiff(u, c, o) == 3
+
+
+def test_stride_checks():
+    u, c, o = spaced(3)
+    u.sj = u.ni + 3        # < ni + 2 hi
+    assert hdiff(u, c, o) == 4
+    u, c, o = spaced(3)
+    u.sk = u.sj * u.nj     # cannot hold the j halo
+    assert hdiff(u, c, o) == 4
+    u, c, o = spaced(3, sj=40)
+    c.sj = 41
+    c.sk = 41 * 16
+    assert hdiff(u, c, o) == 4
+
+
+def test_halo_from_shape_inference():
+    # hdiff reads a 2-cell halo of u (the 13-point diamond); coeff needs none.
+    u, c, o = spaced(3, hi=1, hj=2)
+    assert hdiff(u, c, o) == 5
+    assert "halo" in B.stencil_last_error()
+    fs = spaced(7, hi=1, hj=1)
+    assert fused(fs) == 5
+
+
+def test_alias_checks():
+    u, c, o = spaced(3)
+    o.origin = u.origin
+    assert hdiff(u, c, o) == 6
+    u, c, o = spaced(3)
+    # out's first row overlaps the last plane of u
+    o.origin = u.origin + 4 * (u.sk * (u.nk - 1))
+    assert hdiff(u, c, o) == 6
+    fs = spaced(7)
+    fs[6].origin = fs[3].origin + 4 * 7
+    assert fused(fs) == 6
+
+
+def test_scalar_and_config_checks():
+    u, c, o = spaced(3)
+    assert hdiff(u, c, o, B.config(unroll=3)) == 9
+    assert hdiff(u, c, o, B.config(level=7)) == 9
+    assert fused(spaced(7), dt=float("nan")) == 9
+    assert vadv(spaced(6), dt=float("inf")) == 9
+    assert fused(spaced(7), cfg=B.config(tile_j=3, prefetch=4)) == 7
+
+
+def test_offsets_beyond_32_bits_are_unsupported():
+    u, c, o = spaced(3, ni=2000, nj=2000, nk=600)
+    assert hdiff(u, c, o) == 7
+
+
+def test_empty_interior_is_a_noop():
+    for dims in ((0, 12, 5), (16, 0, 5), (16, 12, 0)):
+        u, c, o = spaced(3, ni=dims[0], nj=dims[1], nk=dims[2])
+        assert hdiff(u, c, o) == 0
+        assert fused(spaced(7, ni=dims[0], nj=dims[1], nk=dims[2])) == 0
+
+
+def test_probe_copy_validation():
+    lib = B.lib()
+    assert lib.stencil_probe_copy(None, ctypes.c_void_p(FAKE), 16, None) == 1
+    assert lib.stencil_probe_copy(ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE + 1024), 17, None) == 9
+    assert lib.stencil_probe_copy(ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE + 16), 64, None) == 6
