@@ -11,7 +11,7 @@ The binding is imported lazily so that ``inputs`` can be used without torch.
 """
 
 _BINDING_NAMES = {
-    "Field", "FieldDesc", "Config", "Program", "Subdomain", "StencilError", "config", "lib",
+    "Field", "FieldDesc", "Config", "Program", "ProgramSpec", "Subdomain", "StencilError", "config", "lib",
     "stencil_hdiff", "stencil_vadv", "stencil_hdiff_vadv", "stencil_hdiff_vadv_adjoint",
     "stencil_program_run", "stencil_probe_copy", "stencil_last_error", "stencil_abi_version",
     "stencil_shutdown", "EXPORTS", "LIB_PATH",

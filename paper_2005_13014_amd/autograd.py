@@ -1,0 +1,57 @@
+"""torch.autograd wrapper of the fused hdiff + vadv program.
+
+The differentiable tensors are the flat device buffers of the fields
+(``Field.buf``), so a gradient lands in the same halo-padded layout as its
+field: the gradient of u covers the interior and the 2-cell ring that the
+13-point diamond reads, those of coeff and wcon the interior; every other
+element of a gradient buffer is zero.  The backward pass is the hand-written
+adjoint (``stencil_hdiff_vadv_adjoint``) with the limiter decisions of the
+forward pass held fixed.  No gradient flows to a, b, c or dt.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+
+def _wrap(buf, like):
+    return B.Field(buf, like.origin, like.ni, like.nj, like.nk, like.hi, like.hj, like.sj, like.sk,
+                   like.dtype)
+
+
+class HdiffVadv(torch.autograd.Function):
+    """x.buf = HdiffVadv.apply(u.buf, coeff.buf, wcon.buf, a.buf, b.buf, c.buf, meta)
+    with meta = (layout, dt): a Field whose layout every field of the call
+    shares (the output and the gradients are allocated with it)."""
+
+    @staticmethod
+    def forward(ctx, u_buf, coeff_buf, wcon_buf, a_buf, b_buf, c_buf, meta):
+        lay, dt = meta
+        x_lay = lay
+        u, coeff, wcon, a, b, c = (_wrap(t, lay) for t in (u_buf, coeff_buf, wcon_buf, a_buf, b_buf,
+                                                           c_buf))
+        x = x_lay.like(fill=0.0)
+        B.stencil_hdiff_vadv(u, coeff, wcon, a, b, c, dt, x)
+        ctx.save_for_backward(u_buf, coeff_buf, wcon_buf, a_buf, b_buf, c_buf)
+        ctx.meta = meta
+        return x.buf
+
+    @staticmethod
+    def backward(ctx, gx_buf):
+        lay, dt = ctx.meta
+        x_lay = lay
+        u, coeff, wcon, a, b, c = (_wrap(t, lay) for t in ctx.saved_tensors)
+        w = _wrap(gx_buf.contiguous(), x_lay)
+        gu, gcoeff, gwcon = (lay.like(fill=0.0) for _ in range(3))
+        B.stencil_hdiff_vadv_adjoint(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon)
+        need = ctx.needs_input_grad
+        return (gu.buf if need[0] else None, gcoeff.buf if need[1] else None,
+                gwcon.buf if need[2] else None, None, None, None, None)
+
+
+def hdiff_vadv(u, coeff, wcon, a, b, c, dt):
+    """Differentiable x = vadv(hdiff(u, coeff), wcon, a, b, c, dt) on Fields;
+    returns a Field whose ``buf`` carries the autograd graph."""
+    buf = HdiffVadv.apply(u.buf, coeff.buf, wcon.buf, a.buf, b.buf, c.buf, (u, float(dt)))
+    return _wrap(buf, u)

@@ -235,7 +235,31 @@ def stencil_hdiff_vadv_adjoint(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon
 
 
 def stencil_program_run(prog, stream=None):
+    if isinstance(prog, ProgramSpec):
+        prog = prog.struct
     _check(lib().stencil_program_run(ctypes.byref(prog), _stream(stream)))
+
+
+class ProgramSpec:
+    """A stencil_program_t built from Fields; keeps the descriptor arrays alive.
+
+    subdomains: list of dicts with Fields 'coeff', 'wcon', 'a', 'b', 'c' and
+    lists of Fields 'u' and 'z' (same length)."""
+
+    def __init__(self, subdomains, stages=STAGE_HDIFF | STAGE_VADV | STAGE_VDIFF | STAGE_HGRAD,
+                 dt=10.0, kappa=0.1, beta_h=0.05, beta_v=0.01, flags=0):
+        self._keep = []
+        subs = (Subdomain * max(1, len(subdomains)))()
+        for q, sd in enumerate(subdomains):
+            n = len(sd["u"])
+            assert len(sd["z"]) == n
+            us = (FieldDesc * max(1, n))(*[f.desc() for f in sd["u"]])
+            zs = (FieldDesc * max(1, n))(*[f.desc() for f in sd["z"]])
+            self._keep += [us, zs]
+            subs[q] = Subdomain(sd["coeff"].desc(), sd["wcon"].desc(), sd["a"].desc(), sd["b"].desc(),
+                                sd["c"].desc(), n, us, zs)
+        self._keep.append(subs)
+        self.struct = Program(len(subdomains), subs, stages, flags, dt, kappa, beta_h, beta_v)
 
 
 def stencil_probe_copy(src, dst, nbytes, stream=None):

@@ -212,23 +212,49 @@ static int run_plain(int dtype, PlainArgs a, hipStream_t st) {
     return launch_status(launch_plain(dtype, a, st), "unfused kernels");
 }
 
-static hipError_t launch_fused(int dtype, const VadvArgs &a, int tj, int pf, hipStream_t st) {
+static hipError_t launch_column(int dtype, bool fused, const ColumnArgs &a, int tj, int pf,
+                                hipStream_t st) {
     switch (dtype) {
-    case STENCIL_F64: return launch_fused_f64(a, tj, pf, st);
-    case STENCIL_F32: return launch_fused_f32(a, tj, pf, st);
-    default: return launch_fused_bf16(a, tj, pf, st);
+    case STENCIL_F64: return launch_column_f64(fused, a, tj, pf, st);
+    case STENCIL_F32: return launch_column_f32(fused, a, tj, pf, st);
+    default: return launch_column_bf16(fused, a, tj, pf, st);
     }
 }
 
-static hipError_t launch_vadv_any(int dtype, const VadvArgs &a, hipStream_t st) {
+static bool column_variant(int dtype, int tj, int pf) {
     switch (dtype) {
-    case STENCIL_F64: return launch_vadv_f64(a, st);
-    case STENCIL_F32: return launch_vadv_f32(a, st);
-    default: return launch_vadv_bf16(a, st);
+    case STENCIL_F64: return column_variant_f64(tj, pf);
+    case STENCIL_F32: return column_variant_f32(tj, pf);
+    default: return column_variant_bf16(tj, pf);
     }
 }
 
-int kmax_column(int dtype) { return dtype == STENCIL_F64 ? KMAX_COLUMN_F64 : KMAX_COLUMN_F32; }
+// Column kernels address every field through a raw buffer of < 2^31 bytes.
+static bool column_fits(const stencil_field_t *f) {
+    const long long cells = static_cast<long long>(f->ni + 3) + static_cast<long long>(f->nj + 3) * f->sj +
+                            static_cast<long long>(f->nk - 1) * f->sk + 1;
+    return cells * static_cast<long long>(elem_size(f->dtype)) < 2147483647LL;
+}
+
+static ColumnArgs column_args(const stencil_field_t *u, const stencil_field_t *coeff,
+                              const stencil_field_t *wcon, const stencil_field_t *a,
+                              const stencil_field_t *b, const stencil_field_t *c,
+                              const stencil_field_t *x, double dt, bool fused) {
+    const long long es = static_cast<long long>(elem_size(u->dtype));
+    ColumnArgs v{};
+    // Fused: u is addressed from its cell (-2, -2, 0), the corner of the ring hdiff reads.
+    v.u = fused ? static_cast<const char *>(u->origin) - (2 + 2 * u->sj) * es : u->origin;
+    v.coeff = coeff ? coeff->origin : nullptr;
+    v.wcon = wcon->origin; v.a = a->origin; v.b = b->origin; v.c = c->origin;
+    v.x = x->origin;
+    v.u_bytes = static_cast<uint32_t>(((u->ni + 3) + (u->nj + 3) * u->sj + (u->nk - 1) * u->sk + 1) * es);
+    v.col_bytes = static_cast<uint32_t>(((u->ni - 1) + (u->nj - 1) * u->sj + (u->nk - 1) * u->sk + 1) * es);
+    v.I = u->ni; v.J = u->nj; v.K = u->nk;
+    v.sj = static_cast<int>(u->sj); v.sk = static_cast<int>(u->sk);
+    v.dt = dt;
+    return v;
+}
+
 
 }  // namespace stl
 
@@ -299,7 +325,7 @@ STENCIL_API int stencil_vadv(const stencil_field_t *h, const stencil_field_t *wc
     if (empty(h)) return STENCIL_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int dtype = h->dtype;
-    if (cf.level == STENCIL_LEVEL_ORIGINAL || h->nk > kmax_column(dtype)) {
+    if (cf.level == STENCIL_LEVEL_ORIGINAL || h->nk > KMAX_COLUMN || !column_fits(h)) {
         PlainArgs p{};
         p.h = h->origin; p.wcon = wcon->origin; p.a = a->origin; p.b = b->origin; p.c = c->origin;
         p.x = x->origin;
@@ -309,13 +335,8 @@ STENCIL_API int stencil_vadv(const stencil_field_t *h, const stencil_field_t *wc
         p.vadv = true;
         return run_plain(dtype, p, st);
     }
-    VadvArgs v{};
-    v.u = h->origin; v.wcon = wcon->origin; v.a = a->origin; v.b = b->origin; v.c = c->origin;
-    v.x = x->origin;
-    v.I = h->ni; v.J = h->nj; v.K = h->nk;
-    v.sj = static_cast<int>(h->sj); v.sk = static_cast<int>(h->sk);
-    v.dt = dt;
-    return launch_status(launch_vadv_any(dtype, v, st), "vadv kernel");
+    const ColumnArgs v = column_args(h, nullptr, wcon, a, b, c, x, dt, false);
+    return launch_status(launch_column(dtype, false, v, 0, 0, st), "vadv kernel");
 }
 
 STENCIL_API int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field_t *coeff,
@@ -332,16 +353,16 @@ STENCIL_API int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field
     if (cf.level < 0 || cf.level > STENCIL_LEVEL_INLINE)
         return fail(STENCIL_E_ARG, "unknown level %d", cf.level);
     const int dtype = u->dtype;
-    int tj = cf.tile_j ? cf.tile_j : 4;
-    int pf = cf.prefetch ? cf.prefetch : (dtype == STENCIL_F64 ? 2 : 4);
-    if (cf.level != STENCIL_LEVEL_ORIGINAL && !fused_variant_compiled(dtype, tj, pf))
+    const int tj = cf.tile_j ? cf.tile_j : 2;
+    const int pf = cf.prefetch ? cf.prefetch : (dtype == STENCIL_F64 ? 2 : 4);
+    if (cf.level != STENCIL_LEVEL_ORIGINAL && !column_variant(dtype, tj, pf))
         return fail(STENCIL_E_UNSUPPORTED, "no compiled fused variant tile_j=%d prefetch=%d", tj, pf);
     if (empty(u)) return STENCIL_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (cf.level == STENCIL_LEVEL_ORIGINAL || u->nk > kmax_column(dtype)) {
+    if (cf.level == STENCIL_LEVEL_ORIGINAL || u->nk > KMAX_COLUMN || !column_fits(u)) {
         if (cf.level == STENCIL_LEVEL_INLINE)
-            return fail(STENCIL_E_UNSUPPORTED, "fused kernel supports nk <= %d for this dtype",
-                        kmax_column(dtype));
+            return fail(STENCIL_E_UNSUPPORTED,
+                        "fused kernel supports nk <= %d and fields below 2 GiB", KMAX_COLUMN);
         PlainArgs p{};
         p.u = u->origin; p.coeff = coeff->origin;
         p.wcon = wcon->origin; p.a = a->origin; p.b = b->origin; p.c = c->origin;
@@ -352,14 +373,39 @@ STENCIL_API int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field
         p.vadv = true;
         return run_plain(dtype, p, st);
     }
-    VadvArgs v{};
-    v.u = u->origin; v.coeff = coeff->origin;
-    v.wcon = wcon->origin; v.a = a->origin; v.b = b->origin; v.c = c->origin;
-    v.x = x->origin;
-    v.I = u->ni; v.J = u->nj; v.K = u->nk;
-    v.sj = static_cast<int>(u->sj); v.sk = static_cast<int>(u->sk);
-    v.dt = dt;
-    return launch_status(launch_fused(dtype, v, tj, pf, st), "fused hdiff+vadv kernel");
+    const ColumnArgs v = column_args(u, coeff, wcon, a, b, c, x, dt, true);
+    return launch_status(launch_column(dtype, true, v, tj, pf, st), "fused hdiff+vadv kernel");
+}
+
+STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stencil_field_t *coeff,
+                                           const stencil_field_t *wcon, const stencil_field_t *a,
+                                           const stencil_field_t *b, const stencil_field_t *c,
+                                           double dt, const stencil_field_t *w,
+                                           const stencil_field_t *gu, const stencil_field_t *gcoeff,
+                                           const stencil_field_t *gwcon, const stencil_config_t *cfg,
+                                           void *stream) {
+    const stencil_field_t *fs[] = {u, coeff, wcon, a, b, c, w, gu, gcoeff, gwcon};
+    const char *names[] = {"u", "coeff", "wcon", "a", "b", "c", "w", "gu", "gcoeff", "gwcon"};
+    TRY(check_call(fs, names, 10, 3));
+    TRY(check_halo(u, "u", 2));
+    TRY(check_halo(gu, "gu", 2));
+    TRY(check_dt(dt));
+    (void)cfg;
+    if (empty(u)) return STENCIL_OK;
+    if (u->nk > KMAX_ADJOINT)
+        return fail(STENCIL_E_UNSUPPORTED, "adjoint supports nk <= %d", KMAX_ADJOINT);
+    if (u->nk > 65535) return fail(STENCIL_E_UNSUPPORTED, "nk too large");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    AdjointArgs x{};
+    x.u = u->origin; x.coeff = coeff->origin; x.wcon = wcon->origin;
+    x.a = a->origin; x.b = b->origin; x.c = c->origin; x.w = w->origin;
+    x.gu = gu->origin; x.gcoeff = gcoeff->origin; x.gwcon = gwcon->origin;
+    x.I = u->ni; x.J = u->nj; x.K = u->nk;
+    x.sj = static_cast<int>(u->sj); x.sk = static_cast<int>(u->sk);
+    x.dt = dt;
+    void *scratch = nullptr;
+    TRY(scratch_get(st, adjoint_scratch_bytes(u->dtype, x.sk, x.K), &scratch));
+    return launch_status(launch_adjoint(u->dtype, x, scratch, st), "adjoint kernels");
 }
 
 STENCIL_API int stencil_probe_copy(const void *src, void *dst, int64_t nbytes, void *stream) {

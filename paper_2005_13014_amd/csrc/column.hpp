@@ -1,24 +1,35 @@
-// Column kernels: the fused hdiff + vadv program and vadv alone.
+// Column kernels: the fused hdiff + vadv program, and vadv alone.
 //
-// One lane owns one (i, j) column and marches up the k levels.  Per level it
-// (1) stages the u tile with its 2-cell halo into LDS (fused kernel only),
-// (2) evaluates the horizontal-diffusion operator from the tile, (3) forms the
-// flux-form right-hand side of the level below, whose upper face needs h one
-// level ahead, and (4) takes one Thomas forward-elimination step in double
-// precision.  The eliminated coefficients c'(k), d'(k) of the whole column
-// stay in registers (the level loop is fully unrolled over a compile-time
-// bound KMAX >= K, so the arrays are only indexed with constants), and the
-// back-substitution then writes x from the top level down.  Every input is
-// read from device memory once and x written once: the temporaries lap, flx,
-// fly, h, d, c', d' never leave the chip (stencil inlining, Sec. V-A).  Inputs
-// of the next PF levels are loaded ahead into a register ring so that many
-// loads stay in flight while a level is being computed.
+// Each (i, j) column is solved by two lanes of one workgroup that meet in the
+// middle (a "burn at both ends" Thomas solve).  With M = ceil(K / 2), the
+// lanes of half 0 march up through levels 0 .. M-1 eliminating top-down, the
+// lanes of half 1 march down through levels K-1 .. M eliminating bottom-up.
+// Per level a lane
+//   (1) stages u of its level, with a 2-cell halo, into LDS (fused kernel),
+//   (2) evaluates horizontal diffusion from the tile (stencil inlining: the
+//       Laplacian and both limited fluxes are recomputed, never stored),
+//   (3) forms the flux-form right-hand side of the level before (whose outer
+//       face needs h one level ahead), and
+//   (4) takes one elimination step in double precision.
+// The interface levels M-1 and M exchange h and w, finish their elimination,
+// then exchange the two eliminated rows
+//     x(M-1) + P0 x(M) = D0,      x(M) + P1 x(M-1) = D1,
+// and solve that 2 x 2 system; each half then back-substitutes outward.
 //
-// Thomas forward elimination (double precision):
-//   k = 0: c'(0) = c(0)/b(0),  d'(0) = d(0)/b(0)
-//   k > 0: m = b(k) - a(k) c'(k-1),  c'(k) = c(k)/m,  d'(k) = (d(k) - a(k) d'(k-1))/m
-// computed with one reciprocal of m per level.  Back-substitution:
-//   x(K-1) = d'(K-1),  x(k) = d'(k) - c'(k) x(k+1), rounded once to storage.
+// Splitting the column halves the double-precision coefficients each lane
+// keeps in registers (the level loop is fully unrolled over a compile-time
+// bound KH >= M so the arrays are only indexed with constants), which lets two
+// waves share each SIMD, and halves the length of each sequential chain.
+// Every input is read from device memory once and x written once (stencil
+// inlining, Sec. V-A).  Inputs of the next PF levels are prefetched into a
+// register ring through buffer loads whose per-level offset is a scalar.
+//
+// Elimination (half 0: lower = a, upper = c; half 1: lower = c, upper = a):
+//   t = 0: P(0) = upper / b,  D(0) = d / b
+//   t > 0: m = b - lower P(t-1),  P(t) = upper / m,  D(t) = (d - lower D(t-1)) / m
+// with 1/m from the hardware reciprocal refined by two Newton steps (error
+// within an ulp).  Back-substitution: x = D(t) - P(t) x(next), rounded once to
+// the storage dtype.
 #pragma once
 
 #include "common.hpp"
@@ -26,252 +37,327 @@
 namespace stl {
 
 // ---------------------------------------------------------------------------
-// Fused hdiff + vadv.  Workgroup = 64 x TJ lanes = a 64 x TJ tile of columns.
+// Raw buffer access (gfx9 family descriptor).  Byte offsets: `vo` per lane,
+// `so` uniform (held in an SGPR, so advancing a level costs no vector work).
 // ---------------------------------------------------------------------------
-template <class T, int TJ, int PF, int KMAX>
-__global__ __launch_bounds__(64 * TJ) void k_hdiff_vadv(VadvArgs p) {
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), static_cast<short>(0),
+                                             static_cast<int>(nbytes), 0x00020000);
+}
+
+template <class T> struct BufIO;
+
+template <> struct BufIO<float> {
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void store_d(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
+                                                   double v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(static_cast<float>(v)), r, vo, so, 0);
+    }
+};
+
+template <> struct BufIO<double> {
+    static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void store_d(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
+                                                   double v) {
+        using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, vo, so, 0);
+    }
+};
+
+template <> struct BufIO<uint16_t> {
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+        const uint32_t b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+        return __uint_as_float(b << 16);
+    }
+    static __device__ __forceinline__ void store_d(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
+                                                   double v) {
+        uint16_t b;
+        Storage<uint16_t>::store_d(&b, v);
+        __builtin_amdgcn_raw_buffer_store_b16(b, r, vo, so, 0);
+    }
+};
+
+// 1/m: hardware reciprocal plus two Newton-Raphson steps.
+__device__ __forceinline__ double recip(double m) {
+    double r = __builtin_amdgcn_rcp(m);
+    double e = __builtin_fma(-m, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-m, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+
+// ---------------------------------------------------------------------------
+// Workgroup = 2 halves x (64 x TJ lanes); the tile is 64 x TJ columns.
+// ---------------------------------------------------------------------------
+// One 64 x TJ tile of columns; VDIFF replaces x by y = x + kappa (x(k+1) -
+// 2 x(k) + x(k-1)) (zero flux through the bottom and top faces), finished
+// level by level during the back-substitution.
+template <class T, bool FUSED, bool VDIFF, int TJ, int PF, int KH>
+__device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj, double kappa) {
     using S = Storage<T>;
     using C = typename S::C;
-    constexpr int TI = 64, PI = TI + 4, PJ = TJ + 4;
-    constexpr int MR = (PJ + TJ - 1) / TJ;  // tile rows loaded per lane (main block)
-    __shared__ C tile[2][PJ * PI];
+    using IO = BufIO<T>;
+    constexpr int TI = 64, PI = TI + 4, PJ = TJ + 4, MR = PJ / TJ, NH = 64 * TJ;
+    static_assert(PJ % TJ == 0, "tile rows must split evenly over the lanes");
+    constexpr int TILE = PJ * PI + 64;  // + one dummy slot per lane of the side-loading wave
+    constexpr uint32_t ES = sizeof(T);
+    __shared__ C tile[FUSED ? 2 * 2 * TILE : 1];
+    __shared__ double2 xch[2 * NH];
 
-    const T *__restrict__ u = static_cast<const T *>(p.u);
-    const T *__restrict__ coeff = static_cast<const T *>(p.coeff);
-    const T *__restrict__ wcon = static_cast<const T *>(p.wcon);
-    const T *__restrict__ fa = static_cast<const T *>(p.a);
-    const T *__restrict__ fb = static_cast<const T *>(p.b);
-    const T *__restrict__ fc = static_cast<const T *>(p.c);
-    T *__restrict__ x = static_cast<T *>(p.x);
-
-    const int tid = threadIdx.x, ti = tid & 63, tj = tid >> 6;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int bi = t % p.nbi, bj = t / p.nbi;
+    const int tid = threadIdx.x;
+    const int half = tid >= NH ? 1 : 0;
+    const int l = tid - half * NH, ti = l & 63, tj = l >> 6;
     const int i0 = bi * TI, j0 = bj * TJ;
     const int gi = i0 + ti, gj = j0 + tj;
     const bool active = gi < p.I && gj < p.J;
+    const int I = p.I, J = p.J, K = p.K, sj = p.sj;
     // Lanes past a ragged edge read a valid column and store nothing.
-    const int col = min(gi, p.I - 1) + min(gj, p.J - 1) * p.sj;
+    const uint32_t vcol = static_cast<uint32_t>(min(gi, I - 1) + min(gj, J - 1) * sj) * ES;
+    const uint32_t sk_bytes = static_cast<uint32_t>(p.sk) * ES;
 
-    // Tile element (r, c) holds u(i0 - 2 + c, j0 - 2 + r).  Main block
-    // c in [2, 66): lane (ti, tj) loads rows tj, tj + TJ, ...; the four side
-    // columns c in {0, 1, 66, 67} are loaded by lanes 0 .. 4 PJ - 1.  Cells
-    // outside [-2, I+2) x [-2, J+2) are never read by an active lane; they get 0.
-    int moff[MR], mlds[MR];
-    bool mrow[MR], mok[MR];
+    const auto ru = make_rsrc(p.u, FUSED ? p.u_bytes : p.col_bytes);
+    const auto rcf = make_rsrc(p.coeff, p.col_bytes);
+    const auto rw = make_rsrc(p.wcon, p.col_bytes);
+    const auto ra = make_rsrc(p.a, p.col_bytes);
+    const auto rb = make_rsrc(p.b, p.col_bytes);
+    const auto rc = make_rsrc(p.c, p.col_bytes);
+    const auto rx = make_rsrc(p.x, p.col_bytes);
+
+    // u tile (fused): element (r, c) holds u(i0 - 2 + c, j0 - 2 + r).  Main block
+    // c in [2, 66): lane (ti, tj) stages rows tj, tj + TJ, ...; the four side
+    // columns c in {0, 1, 66, 67} are staged by the first 4 PJ lanes of the
+    // half's first wave (its other lanes write a dummy slot).  Cells past
+    // [-2, I+2) x [-2, J+2) are never read by an active lane: their loads are
+    // clamped onto valid cells instead of being predicated.
+    uint32_t vmain[MR];
+    int lmain[MR];
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
-        const int r = tj + m * TJ, gy = j0 - 2 + r;
-        mrow[m] = r < PJ;
-        mok[m] = mrow[m] && gi < p.I + 2 && gy < p.J + 2;
-        moff[m] = gi + gy * p.sj;
-        mlds[m] = r * PI + ti + 2;
+        const int r = tj + m * TJ;
+        const int gx = min(gi, I + 1), gy = min(j0 - 2 + r, J + 1);
+        vmain[m] = static_cast<uint32_t>(gx + 2 + (gy + 2) * sj) * ES;
+        lmain[m] = r * PI + ti + 2;
     }
-    const int sr = tid >> 2, sq = tid & 3;
+    const bool side_wave = tj == 0;
+    const int sr = min(l >> 2, PJ - 1), sq = l & 3;
     const int sc = sq < 2 ? sq : sq + 64;
-    const int sgx = i0 - 2 + sc, sgy = j0 - 2 + sr;
-    const bool srow = tid < 4 * PJ;
-    const bool sok = srow && sgx < p.I + 2 && sgy < p.J + 2;
-    const int soff = sgx + sgy * p.sj;
-    const int slds = sr * PI + sc;
+    const uint32_t vside =
+        static_cast<uint32_t>(min(i0 - 2 + sc, I + 1) + 2 + (min(j0 - 2 + sr, J + 1) + 2) * sj) * ES;
+    const int lside = l < 4 * PJ ? sr * PI + sc : PJ * PI + ti;
 
-    // Prefetch ring: slot q holds the inputs of every level s with s % PF == q.
-    C rum[PF][MR], rus[PF], rcf[PF], rw[PF], ra[PF], rb[PF], rc[PF];
-    auto load = [&](int q, int k) {
-        const int ko = k * p.sk;
+    const int M = (K + 1) >> 1;
+    const int nsteps = half ? K - M : M;
+    auto level = [&](int s) { return half ? K - 1 - s : s; };
+
+    C rum[PF][FUSED ? MR : 1], rus[PF], rcfv[PF], rwv[PF], rav[PF], rbv[PF], rcv[PF];
+    auto load = [&](int q, int s) {
+        const uint32_t so = static_cast<uint32_t>(level(s)) * sk_bytes;
+        if constexpr (FUSED) {
 #pragma unroll
-        for (int m = 0; m < MR; ++m) rum[q][m] = mok[m] ? S::load(u + moff[m] + ko) : C(0);
-        rus[q] = sok ? S::load(u + soff + ko) : C(0);
-        rcf[q] = S::load(coeff + col + ko);
-        rw[q] = S::load(wcon + col + ko);
-        ra[q] = S::load(fa + col + ko);
-        rb[q] = S::load(fb + col + ko);
-        rc[q] = S::load(fc + col + ko);
+            for (int m = 0; m < MR; ++m) rum[q][m] = IO::load(ru, vmain[m], so);
+            if (side_wave) rus[q] = IO::load(ru, vside, so);
+            rcfv[q] = IO::load(rcf, vcol, so);
+        } else {
+            rum[q][0] = IO::load(ru, vcol, so);
+        }
+        rwv[q] = IO::load(rw, vcol, so);
+        rav[q] = IO::load(ra, vcol, so);
+        rbv[q] = IO::load(rb, vcol, so);
+        rcv[q] = IO::load(rc, vcol, so);
     };
-
-    const int K = p.K;
 #pragma unroll
     for (int q = 0; q < PF; ++q)
-        if (q < K) load(q, q);
+        if (q < nsteps) load(q, q);
 
     const C dt = static_cast<C>(p.dt);
-    C h_prev = C(0), w_prev = C(0), f_prev = C(0);
-    double a_prev = 0.0, b_prev = 1.0, c_prev = 0.0;
-    double cp[KMAX], dp[KMAX];
+    C h_prev = C(0), w_prev = C(0), f_old = C(0);
+    double lo_prev = 0.0, b_prev = 1.0, up_prev = 0.0;
+    double P[KH], D[KH];
+    double P_last = 0.0, D_last = 0.0;  // row t - 1 of the running elimination
 
 #pragma unroll
-    for (int s = 0; s < KMAX; ++s) {
-        if (s < K) {
+    for (int s = 0; s < KH; ++s) {
+        if (s < M) {
+            const bool on = s < nsteps;
             const int q = s % PF;
-            C *tb = tile[s & 1];
+            C *tb = &tile[(half * 2 + (s & 1)) * TILE];
+            if constexpr (FUSED) {
+                if (on) {
 #pragma unroll
-            for (int m = 0; m < MR; ++m)
-                if (mrow[m]) tb[mlds[m]] = rum[q][m];
-            if (srow) tb[slds] = rus[q];
-            const C cf = rcf[q], wv = rw[q];
-            const double av = static_cast<double>(ra[q]), bv = static_cast<double>(rb[q]),
-                         cv = static_cast<double>(rc[q]);
-            if (s + PF < K) load(q, s + PF);
-            __syncthreads();
-            const C h = hdiff_point<C, PI>(tb + (tj + 2) * PI + ti + 2, cf);
-            if (s > 0) {
-                // F(s - 1/2), then the right-hand side and elimination of level s - 1.
-                const int l = s > 0 ? s - 1 : 0;
-                const C f = (C(0.5) * (w_prev + wv)) * (C(0.5) * (h_prev + h));
-                const double d = static_cast<double>(h_prev - dt * (f - f_prev));
-                if (l == 0) {
-                    const double r = 1.0 / b_prev;
-                    cp[0] = c_prev * r;
-                    dp[0] = d * r;
-                } else {
-                    const int lm = l > 0 ? l - 1 : 0;
-                    const double r = 1.0 / (b_prev - a_prev * cp[lm]);
-                    cp[l] = c_prev * r;
-                    dp[l] = (d - a_prev * dp[lm]) * r;
-                }
-                f_prev = f;
-            }
-            if (s == K - 1) {
-                // Top level: no flux through the upper face.
-                const double d = static_cast<double>(h - dt * (C(0) - f_prev));
-                if (s == 0) {
-                    dp[0] = d / bv;
-                } else {
-                    const int lm = s > 0 ? s - 1 : 0;
-                    dp[s] = (d - av * dp[lm]) / (bv - av * cp[lm]);
+                    for (int m = 0; m < MR; ++m) tb[lmain[m]] = rum[q][m];
+                    if (side_wave) tb[lside] = rus[q];
                 }
             }
-            h_prev = h;
-            w_prev = wv;
-            a_prev = av;
-            b_prev = bv;
-            c_prev = cv;
+            const C hv = FUSED ? C(0) : rum[q][0];
+            const C cf = FUSED ? rcfv[q] : C(0);
+            const C wv = rwv[q];
+            const double av = static_cast<double>(rav[q]), bv = static_cast<double>(rbv[q]),
+                         cv = static_cast<double>(rcv[q]);
+            if (s + PF < nsteps) load(q, s + PF);
+            if constexpr (FUSED) __syncthreads();
+            if (on) {
+                const C h = FUSED ? hdiff_point<C, PI>(tb + (tj + 2) * PI + ti + 2, cf) : hv;
+                if (s > 0) {
+                    // Face between the previous and this level; right-hand side
+                    // and elimination of the previous level.
+                    const C f_new = (C(0.5) * (w_prev + wv)) * (C(0.5) * (h_prev + h));
+                    const C diff = half ? (f_old - f_new) : (f_new - f_old);
+                    const double d = static_cast<double>(h_prev - dt * diff);
+                    const int tt = s > 0 ? s - 1 : 0;
+                    if (tt == 0) {
+                        const double r = recip(b_prev);
+                        P[0] = up_prev * r;
+                        D[0] = d * r;
+                    } else {
+                        const int tm = tt > 0 ? tt - 1 : 0;
+                        const double r = recip(b_prev - lo_prev * P[tm]);
+                        P[tt] = up_prev * r;
+                        D[tt] = (d - lo_prev * D[tm]) * r;
+                    }
+                    P_last = P[tt];
+                    D_last = D[tt];
+                    f_old = f_new;
+                }
+                h_prev = h;
+                w_prev = wv;
+                lo_prev = half ? cv : av;
+                up_prev = half ? av : cv;
+                b_prev = bv;
+            }
         }
     }
 
-    double xn = 0.0;
+    // Interface, part 1: the face between levels M-1 and M.
+    xch[tid] = make_double2(static_cast<double>(h_prev), static_cast<double>(w_prev));
+    __syncthreads();
+    const double2 o1 = xch[half ? l : NH + l];
+    C f_mid = C(0);
+    if (K - M > 0)
+        f_mid = (C(0.5) * (w_prev + static_cast<C>(o1.y))) * (C(0.5) * (h_prev + static_cast<C>(o1.x)));
+    double Pm = 0.0, Dm = 0.0;  // this half's eliminated interface row
+    if (nsteps > 0) {
+        const C diff = half ? (f_old - f_mid) : (f_mid - f_old);
+        const double d = static_cast<double>(h_prev - dt * diff);
+        const double m = nsteps > 1 ? b_prev - lo_prev * P_last : b_prev;
+        const double r = recip(m);
+        Pm = up_prev * r;
+        Dm = (nsteps > 1 ? d - lo_prev * D_last : d) * r;
+    }
+    __syncthreads();
+    // Interface, part 2: x(M-1) + P0 x(M) = D0 and x(M) + P1 x(M-1) = D1.
+    xch[tid] = make_double2(Pm, Dm);
+    __syncthreads();
+    const double2 o2 = xch[half ? l : NH + l];
+    const double P0 = half ? o2.x : Pm, D0 = half ? o2.y : Dm;
+    const double P1 = half ? Pm : o2.x, D1 = half ? Dm : o2.y;
+    const double x_lo = (D0 - P0 * D1) / (1.0 - P0 * P1);  // x(M-1)
+    const double x_hi = D1 - P1 * x_lo;                     // x(M)
+
+    // Back-substitution outward from the interface.  Local index t counts
+    // from the far end of this half's levels (level(t)); the walk runs from
+    // t = nsteps - 1 (the interface) down to t = 0.
+    double xn = half ? x_hi : x_lo;
+    if constexpr (!VDIFF) {
+        if (active && nsteps > 0)
+            IO::store_d(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, xn);
 #pragma unroll
-    for (int s = KMAX - 1; s >= 0; --s) {
-        if (s < K) {
-            xn = (s == K - 1) ? dp[s] : dp[s] - cp[s] * xn;
-            if (active) S::store_d(x + col + s * p.sk, xn);
+        for (int tt = KH - 2; tt >= 0; --tt) {
+            if (tt < nsteps - 1) {
+                xn = D[tt] - P[tt] * xn;
+                if (active) IO::store_d(rx, vcol, static_cast<uint32_t>(level(tt)) * sk_bytes, xn);
+            }
         }
+    } else {
+        // y at local index t + 1 is finished once x(t) is known: its neighbour
+        // toward the interface is x(t + 2) (the other half's interface value
+        // for t + 1 = nsteps - 1), away from it x(t).  Half 0 walks down
+        // (toward = up), half 1 walks up (toward = down).
+        const bool has_other = K > 1;
+        double x_in = half ? x_lo : x_hi;  // toward-interface neighbour of the current level
+        double x_cur = xn;
+        auto finish = [&](int t_loc, double toward, bool has_toward, double away, bool has_away) {
+            const double up = half ? away : toward, dn = half ? toward : away;
+            const bool has_up = half ? has_away : has_toward, has_dn = half ? has_toward : has_away;
+            const double g_up = has_up ? up - x_cur : 0.0;
+            const double g_dn = has_dn ? x_cur - dn : 0.0;
+            const double y = x_cur + kappa * (g_up - g_dn);
+            if (active) IO::store_d(rx, vcol, static_cast<uint32_t>(level(t_loc)) * sk_bytes, y);
+        };
+#pragma unroll
+        for (int tt = KH - 2; tt >= 0; --tt) {
+            if (tt < nsteps - 1) {
+                const double xt = D[tt] - P[tt] * x_cur;
+                finish(tt + 1, x_in, tt + 1 < nsteps - 1 || has_other, xt, true);
+                x_in = x_cur;
+                x_cur = xt;
+            }
+        }
+        if (nsteps > 0) finish(0, x_in, nsteps > 1 || has_other, 0.0, false);
     }
 }
 
-// ---------------------------------------------------------------------------
-// vadv alone: h is read from memory.  Workgroup = 64 x TJ columns.
-// ---------------------------------------------------------------------------
-template <class T, int TJ, int PF, int KMAX>
-__global__ __launch_bounds__(64 * TJ) void k_vadv(VadvArgs p) {
-    using S = Storage<T>;
-    using C = typename S::C;
-    const T *__restrict__ hin = static_cast<const T *>(p.u);
-    const T *__restrict__ wcon = static_cast<const T *>(p.wcon);
-    const T *__restrict__ fa = static_cast<const T *>(p.a);
-    const T *__restrict__ fb = static_cast<const T *>(p.b);
-    const T *__restrict__ fc = static_cast<const T *>(p.c);
-    T *__restrict__ x = static_cast<T *>(p.x);
-
-    const int tid = threadIdx.x, ti = tid & 63, tj = tid >> 6;
+template <class T, bool FUSED, int TJ, int PF, int KH, int WPE>
+__global__ __launch_bounds__(128 * TJ) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void
+k_column(ColumnArgs p) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int bi = t % p.nbi, bj = t / p.nbi;
-    const int gi = bi * 64 + ti, gj = bj * TJ + tj;
-    const bool active = gi < p.I && gj < p.J;
-    const int col = min(gi, p.I - 1) + min(gj, p.J - 1) * p.sj;
+    column_tile<T, FUSED, false, TJ, PF, KH>(p, t % p.nbi, t / p.nbi, 0.0);
+}
 
-    C rh[PF], rw[PF], ra[PF], rb[PF], rc[PF];
-    auto load = [&](int q, int k) {
-        const int o = col + k * p.sk;
-        rh[q] = S::load(hin + o);
-        rw[q] = S::load(wcon + o);
-        ra[q] = S::load(fa + o);
-        rb[q] = S::load(fb + o);
-        rc[q] = S::load(fc + o);
-    };
-    const int K = p.K;
-#pragma unroll
-    for (int q = 0; q < PF; ++q)
-        if (q < K) load(q, q);
+// ---------------------------------------------------------------------------
+// Batched form: many (subdomain, field) problems in one launch.  The tiles of
+// all problems are numbered consecutively, subdomain by subdomain, with the
+// field index fastest, so the workgroups of the fields that share a
+// subdomain's coefficient fields run next to each other on one XCD (the
+// tile map keeps consecutive tiles on the same XCD) and share those loads in
+// its L2.  The table travels in the kernel arguments.
+// ---------------------------------------------------------------------------
+constexpr int BATCH_SUBS = 8;
+constexpr int BATCH_FIELDS = 8;
 
-    const C dt = static_cast<C>(p.dt);
-    C h_prev = C(0), w_prev = C(0), f_prev = C(0);
-    double a_prev = 0.0, b_prev = 1.0, c_prev = 0.0;
-    double cp[KMAX], dp[KMAX];
+struct ColumnBatchSub {
+    ColumnArgs a;                        // shared coefficients; u, x unused
+    const void *u[BATCH_FIELDS];
+    void *x[BATCH_FIELDS];
+    int tile0;                           // first batch tile of this subdomain
+    int nfields;
+};
 
-#pragma unroll
-    for (int s = 0; s < KMAX; ++s) {
-        if (s < K) {
-            const int q = s % PF;
-            const C h = rh[q], wv = rw[q];
-            const double av = static_cast<double>(ra[q]), bv = static_cast<double>(rb[q]),
-                         cv = static_cast<double>(rc[q]);
-            if (s + PF < K) load(q, s + PF);
-            if (s > 0) {
-                const int l = s > 0 ? s - 1 : 0;
-                const C f = (C(0.5) * (w_prev + wv)) * (C(0.5) * (h_prev + h));
-                const double d = static_cast<double>(h_prev - dt * (f - f_prev));
-                if (l == 0) {
-                    const double r = 1.0 / b_prev;
-                    cp[0] = c_prev * r;
-                    dp[0] = d * r;
-                } else {
-                    const int lm = l > 0 ? l - 1 : 0;
-                    const double r = 1.0 / (b_prev - a_prev * cp[lm]);
-                    cp[l] = c_prev * r;
-                    dp[l] = (d - a_prev * dp[lm]) * r;
-                }
-                f_prev = f;
-            }
-            if (s == K - 1) {
-                const double d = static_cast<double>(h - dt * (C(0) - f_prev));
-                if (s == 0) {
-                    dp[0] = d / bv;
-                } else {
-                    const int lm = s > 0 ? s - 1 : 0;
-                    dp[s] = (d - av * dp[lm]) / (bv - av * cp[lm]);
-                }
-            }
-            h_prev = h;
-            w_prev = wv;
-            a_prev = av;
-            b_prev = bv;
-            c_prev = cv;
-        }
-    }
+struct ColumnBatch {
+    ColumnBatchSub sub[BATCH_SUBS];
+    int nsub;
+    double kappa;
+};
 
-    double xn = 0.0;
-#pragma unroll
-    for (int s = KMAX - 1; s >= 0; --s) {
-        if (s < K) {
-            xn = (s == K - 1) ? dp[s] : dp[s] - cp[s] * xn;
-            if (active) S::store_d(x + col + s * p.sk, xn);
-        }
-    }
+template <class T, bool VDIFF, int TJ, int PF, int KH, int WPE>
+__global__ __launch_bounds__(128 * TJ) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void
+k_column_batch(ColumnBatch b) {
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    int s = 0;
+    while (s + 1 < b.nsub && b.sub[s + 1].tile0 <= t) ++s;
+    const ColumnBatchSub &sb = b.sub[s];
+    const int local = t - sb.tile0;
+    const int f = local % sb.nfields, tile = local / sb.nfields;
+    ColumnArgs a = sb.a;
+    a.u = sb.u[f];
+    a.x = sb.x[f];
+    column_tile<T, true, VDIFF, TJ, PF, KH>(a, tile % a.nbi, tile / a.nbi, b.kappa);
 }
 
 // ---------------------------------------------------------------------------
 // Host launchers, instantiated per storage type in column_<dtype>.hip.
 // ---------------------------------------------------------------------------
-template <class T, int TJ, int PF, int KMAX>
-static hipError_t launch_fused_t(VadvArgs a, hipStream_t st) {
+template <class T, bool FUSED, int TJ, int PF, int KH, int WPE>
+static hipError_t launch_column_t(ColumnArgs a, hipStream_t st) {
     a.nbi = (a.I + 63) / 64;
     a.nbj = (a.J + TJ - 1) / TJ;
-    hipLaunchKernelGGL((k_hdiff_vadv<T, TJ, PF, KMAX>), dim3(a.nbi * a.nbj), dim3(64 * TJ), 0, st,
-                       a);
+    hipLaunchKernelGGL((k_column<T, FUSED, TJ, PF, KH, WPE>), dim3(a.nbi * a.nbj), dim3(128 * TJ), 0,
+                       st, a);
     return hipGetLastError();
 }
-
-template <class T, int TJ, int PF, int KMAX>
-static hipError_t launch_vadv_t(VadvArgs a, hipStream_t st) {
-    a.nbi = (a.I + 63) / 64;
-    a.nbj = (a.J + TJ - 1) / TJ;
-    hipLaunchKernelGGL((k_vadv<T, TJ, PF, KMAX>), dim3(a.nbi * a.nbj), dim3(64 * TJ), 0, st, a);
-    return hipGetLastError();
-}
-
-// Register-resident columns are compiled for these vertical extents.
-#define STL_FOR_KMAX(K, F) \
-    ((K) <= 32 ? F(32) : (K) <= 64 ? F(64) : (K) <= 80 ? F(80) : F(96))
 
 }  // namespace stl

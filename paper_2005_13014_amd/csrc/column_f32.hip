@@ -1,31 +1,37 @@
-// Column kernels instantiated for float storage.
+// Column kernels (column.hpp) instantiated for float storage.
 #include "column.hpp"
 #include "launch.hpp"
 
 namespace stl {
 
-template <int TJ, int PF>
-static hipError_t fused_k(const VadvArgs &a, hipStream_t st) {
-    if (a.K <= 32) return launch_fused_t<float, TJ, PF, 32>(a, st);
-    if (a.K <= 64) return launch_fused_t<float, TJ, PF, 64>(a, st);
-    if (a.K <= 80) return launch_fused_t<float, TJ, PF, 80>(a, st);
-    return launch_fused_t<float, TJ, PF, 96>(a, st);
+// Register-resident half columns of KH levels serve nk <= 2 KH.
+template <bool FUSED, int TJ, int PF>
+static hipError_t by_levels(const ColumnArgs &a, hipStream_t st) {
+    const int m = (a.K + 1) / 2;
+    if (m <= 16) return launch_column_t<float, FUSED, TJ, PF, 16, 2>(a, st);
+    if (m <= 32) return launch_column_t<float, FUSED, TJ, PF, 32, 2>(a, st);
+    if (m <= 40) return launch_column_t<float, FUSED, TJ, PF, 40, 2>(a, st);
+    return launch_column_t<float, FUSED, TJ, PF, 48, 1>(a, st);
 }
 
-hipError_t launch_fused_f32(const VadvArgs &a, int tile_j, int prefetch, hipStream_t st) {
-    if (tile_j == 4 && prefetch == 4) return fused_k<4, 4>(a, st);
-    if (tile_j == 4 && prefetch == 2) return fused_k<4, 2>(a, st);
-    if (tile_j == 4 && prefetch == 8) return fused_k<4, 8>(a, st);
-    if (tile_j == 2 && prefetch == 4) return fused_k<2, 4>(a, st);
-    if (tile_j == 1 && prefetch == 8) return fused_k<1, 8>(a, st);
+bool column_variant_f32(int tile_j, int prefetch) {
+    if (tile_j == 2 && prefetch == 4) return true;
+    if (tile_j == 4 && prefetch == 4) return true;
+    if (tile_j == 2 && prefetch == 2) return true;
+    if (tile_j == 2 && prefetch == 8) return true;
+    if (tile_j == 1 && prefetch == 4) return true;
+    return false;
+}
+
+hipError_t launch_column_f32(bool fused, const ColumnArgs &a, int tile_j, int prefetch,
+                             hipStream_t st) {
+    if (!fused) return by_levels<false, 2, 4>(a, st);
+    if (tile_j == 2 && prefetch == 4) return by_levels<true, 2, 4>(a, st);
+    if (tile_j == 4 && prefetch == 4) return by_levels<true, 4, 4>(a, st);
+    if (tile_j == 2 && prefetch == 2) return by_levels<true, 2, 2>(a, st);
+    if (tile_j == 2 && prefetch == 8) return by_levels<true, 2, 8>(a, st);
+    if (tile_j == 1 && prefetch == 4) return by_levels<true, 1, 4>(a, st);
     return hipErrorInvalidValue;
-}
-
-hipError_t launch_vadv_f32(const VadvArgs &a, hipStream_t st) {
-    if (a.K <= 32) return launch_vadv_t<float, 4, 4, 32>(a, st);
-    if (a.K <= 64) return launch_vadv_t<float, 4, 4, 64>(a, st);
-    if (a.K <= 80) return launch_vadv_t<float, 4, 4, 80>(a, st);
-    return launch_vadv_t<float, 4, 4, 96>(a, st);
 }
 
 }  // namespace stl

@@ -1,25 +1,31 @@
-// Column kernels instantiated for double storage.
+// Column kernels (column.hpp) instantiated for double storage.
 #include "column.hpp"
 #include "launch.hpp"
 
 namespace stl {
 
-template <int TJ, int PF>
-static hipError_t fused_k(const VadvArgs &a, hipStream_t st) {
-    if (a.K <= 32) return launch_fused_t<double, TJ, PF, 32>(a, st);
-    if (a.K <= 64) return launch_fused_t<double, TJ, PF, 64>(a, st);
-    return launch_fused_t<double, TJ, PF, 80>(a, st);
+// Register-resident half columns of KH levels serve nk <= 2 KH.
+template <bool FUSED, int TJ, int PF>
+static hipError_t by_levels(const ColumnArgs &a, hipStream_t st) {
+    const int m = (a.K + 1) / 2;
+    if (m <= 16) return launch_column_t<double, FUSED, TJ, PF, 16, 2>(a, st);
+    if (m <= 32) return launch_column_t<double, FUSED, TJ, PF, 32, 1>(a, st);
+    if (m <= 40) return launch_column_t<double, FUSED, TJ, PF, 40, 1>(a, st);
+    return launch_column_t<double, FUSED, TJ, PF, 48, 1>(a, st);
 }
 
-hipError_t launch_fused_f64(const VadvArgs &a, int tile_j, int prefetch, hipStream_t st) {
-    if (tile_j == 4 && prefetch == 2) return fused_k<4, 2>(a, st);
+bool column_variant_f64(int tile_j, int prefetch) {
+    if (tile_j == 2 && prefetch == 2) return true;
+    if (tile_j == 2 && prefetch == 4) return true;
+    return false;
+}
+
+hipError_t launch_column_f64(bool fused, const ColumnArgs &a, int tile_j, int prefetch,
+                             hipStream_t st) {
+    if (!fused) return by_levels<false, 2, 2>(a, st);
+    if (tile_j == 2 && prefetch == 2) return by_levels<true, 2, 2>(a, st);
+    if (tile_j == 2 && prefetch == 4) return by_levels<true, 2, 4>(a, st);
     return hipErrorInvalidValue;
-}
-
-hipError_t launch_vadv_f64(const VadvArgs &a, hipStream_t st) {
-    if (a.K <= 32) return launch_vadv_t<double, 4, 2, 32>(a, st);
-    if (a.K <= 64) return launch_vadv_t<double, 4, 2, 64>(a, st);
-    return launch_vadv_t<double, 4, 2, 80>(a, st);
 }
 
 }  // namespace stl

@@ -108,11 +108,13 @@ struct HdiffArgs {
     int nbi, nbj;  // tiles in i and j
 };
 
-struct VadvArgs {
-    const void *u;      // u (fused: hdiff input) or h (vadv alone)
-    const void *coeff;  // fused only
-    const void *wcon, *a, *b, *c;
-    void *x;
+// Column kernels (fused hdiff + vadv, vadv alone); see column.hpp.
+struct ColumnArgs {
+    const void *u;  // fused: u at interior (-2, -2, 0); vadv alone: h at its origin
+    const void *coeff, *wcon, *a, *b, *c;  // interior origins
+    void *x;                               // interior origin
+    uint32_t u_bytes;                      // addressable bytes from u
+    uint32_t col_bytes;                    // addressable bytes from an interior origin
     int I, J, K, sj, sk;
     int nbi, nbj;
     double dt;

@@ -9,6 +9,8 @@
 // own column is computed once for the UJ + 2 rows it touches, and each
 // j-flux is computed once and used by the two points on either side of it.
 // The inputs of the next PF levels are prefetched into registers.
+#include <type_traits>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -24,7 +26,8 @@ __device__ __forceinline__ C limit(C f, C du) {
     return (f * du > C(0)) ? C(0) : f;
 }
 
-template <class T, int TJ, int UJ, int PF>
+// TO = T writes the storage dtype; TO = C keeps the compute type (scratch).
+template <class T, class TO, int TJ, int UJ, int PF>
 __global__ __launch_bounds__(64 * TJ) void k_hdiff(HdiffArgs p) {
     using S = Storage<T>;
     using C = typename S::C;
@@ -34,7 +37,7 @@ __global__ __launch_bounds__(64 * TJ) void k_hdiff(HdiffArgs p) {
 
     const T *__restrict__ u = static_cast<const T *>(p.u);
     const T *__restrict__ coeff = static_cast<const T *>(p.coeff);
-    T *__restrict__ out = static_cast<T *>(p.out);
+    TO *__restrict__ out = static_cast<TO *>(p.out);
 
     const int tid = threadIdx.x, ti = tid & 63, tj = tid >> 6;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -120,18 +123,23 @@ __global__ __launch_bounds__(64 * TJ) void k_hdiff(HdiffArgs p) {
                     const C fe = limit(le - lc[v + 1], cv[1] - uc[v + 1]);
                     const C fw = limit(lc[v + 1] - lw, uc[v + 1] - cv[-1]);
                     const C h = uc[v + 1] - cf[v] * (fe - fw + fy[v + 1] - fy[v]);
-                    if (cact[v]) S::store(out + coff[v] + k * p.sk, h);
+                    if (cact[v]) {
+                        if constexpr (std::is_same<TO, C>::value)
+                            out[coff[v] + k * p.sk] = h;
+                        else
+                            S::store(out + coff[v] + k * p.sk, h);
+                    }
                 }
             }
         }
     }
 }
 
-template <class T, int TJ, int UJ, int PF>
+template <class T, int TJ, int UJ, int PF, class TO = T>
 static hipError_t launch_hdiff_t(HdiffArgs a, hipStream_t st) {
     a.nbi = (a.I + 63) / 64;
     a.nbj = (a.J + TJ * UJ - 1) / (TJ * UJ);
-    hipLaunchKernelGGL((k_hdiff<T, TJ, UJ, PF>), dim3(a.nbi * a.nbj), dim3(64 * TJ), 0, st, a);
+    hipLaunchKernelGGL((k_hdiff<T, TO, TJ, UJ, PF>), dim3(a.nbi * a.nbj), dim3(64 * TJ), 0, st, a);
     return hipGetLastError();
 }
 
@@ -141,6 +149,15 @@ static hipError_t hdiff_unroll(const HdiffArgs &a, int unroll, hipStream_t st) {
     case 1: return launch_hdiff_t<T, 4, 1, 4>(a, st);
     case 2: return launch_hdiff_t<T, 4, 2, 4>(a, st);
     case 4: return launch_hdiff_t<T, 4, 4, 4>(a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_hdiff_compute(int dtype, const HdiffArgs &a, hipStream_t st) {
+    switch (dtype) {
+    case DT_F64: return launch_hdiff_t<double, 4, 1, 4, double>(a, st);
+    case DT_F32: return launch_hdiff_t<float, 4, 1, 4, float>(a, st);
+    case DT_BF16: return launch_hdiff_t<uint16_t, 4, 1, 4, float>(a, st);
     }
     return hipErrorInvalidValue;
 }

@@ -10,30 +10,20 @@ namespace stl {
 
 enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
 
-// Largest vertical extent of the register-resident column kernels, per dtype.
-constexpr int KMAX_COLUMN_F64 = 80;
-constexpr int KMAX_COLUMN_F32 = 96;
-
-// (tile_j, prefetch) variants of the fused kernel compiled per dtype
-// (column_<dtype>.hip).
-inline bool fused_variant_compiled(int dtype, int tj, int pf) {
-    if (dtype == DT_F64) return tj == 4 && pf == 2;
-    if (dtype == DT_BF16) return tj == 4 && pf == 4;
-    return (tj == 4 && (pf == 2 || pf == 4 || pf == 8)) || (tj == 2 && pf == 4) ||
-           (tj == 1 && pf == 8);
-}
-
-// Fused hdiff + vadv (column.hpp); (tile_j, prefetch) picks a compiled variant.
-hipError_t launch_fused_f64(const VadvArgs &a, int tile_j, int prefetch, hipStream_t st);
-hipError_t launch_fused_f32(const VadvArgs &a, int tile_j, int prefetch, hipStream_t st);
-hipError_t launch_fused_bf16(const VadvArgs &a, int tile_j, int prefetch, hipStream_t st);
-// vadv alone (column.hpp).
-hipError_t launch_vadv_f64(const VadvArgs &a, hipStream_t st);
-hipError_t launch_vadv_f32(const VadvArgs &a, hipStream_t st);
-hipError_t launch_vadv_bf16(const VadvArgs &a, hipStream_t st);
+// Column kernels (column.hpp): register-resident half columns serve
+// nk <= KMAX_COLUMN; (tile_j, prefetch) selects a compiled fused variant.
+constexpr int KMAX_COLUMN = 96;
+bool column_variant_f64(int tile_j, int prefetch);
+bool column_variant_f32(int tile_j, int prefetch);
+bool column_variant_bf16(int tile_j, int prefetch);
+hipError_t launch_column_f64(bool fused, const ColumnArgs &a, int tile_j, int prefetch, hipStream_t st);
+hipError_t launch_column_f32(bool fused, const ColumnArgs &a, int tile_j, int prefetch, hipStream_t st);
+hipError_t launch_column_bf16(bool fused, const ColumnArgs &a, int tile_j, int prefetch, hipStream_t st);
 
 // Horizontal diffusion alone, inlined, with j-unroll 1, 2 or 4 (hdiff.hip).
 hipError_t launch_hdiff(int dtype, const HdiffArgs &a, int unroll, hipStream_t st);
+// Same operator, result kept in the compute type (double for F64, else float).
+hipError_t launch_hdiff_compute(int dtype, const HdiffArgs &a, hipStream_t st);
 
 // The "original" level: one kernel per operator through device scratch
 // (plain.hip).  u == nullptr runs vadv alone on h; vadv == false runs hdiff
@@ -48,6 +38,18 @@ struct PlainArgs {
 };
 size_t plain_scratch_bytes(int dtype, int I, int J, int K, bool vadv);
 hipError_t launch_plain(int dtype, const PlainArgs &a, hipStream_t st);
+
+// Reverse mode of the fused program (adjoint.hip).  All fields share strides;
+// gu has a halo of at least 2.  scratch: adjoint_scratch_bytes() bytes.
+struct AdjointArgs {
+    const void *u, *coeff, *wcon, *a, *b, *c, *w;
+    void *gu, *gcoeff, *gwcon;
+    int I, J, K, sj, sk;
+    double dt;
+};
+constexpr int KMAX_ADJOINT = 96;
+size_t adjoint_scratch_bytes(int dtype, int sk, int K);
+hipError_t launch_adjoint(int dtype, const AdjointArgs &a, void *scratch, hipStream_t st);
 
 // Streaming copy used as the bandwidth probe (probe.hip).
 hipError_t launch_probe_copy(const void *src, void *dst, long long nbytes, hipStream_t st);

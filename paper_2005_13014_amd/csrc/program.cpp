@@ -1,27 +1,473 @@
-// Batched timestep program (stencil_program_run) -- placeholder until built.
+// Batched timestep program: stencil_program_run.
+//
+// A program applies the stage chain hdiff -> vadv [-> vdiff [-> hgrad]] to
+// every field of every subdomain.  Shape inference (Sec. V-B) grows the
+// domain of the column stages by one cell when hgrad follows, since hgrad
+// reads y on the interior and its 1-cell ring.  Planning:
+//   - the column stages (hdiff + vadv, with vdiff folded into the
+//     back-substitution) run as batched launches, one per register bucket of
+//     the column height, each over a table of up to BATCH_SUBS subdomains x
+//     BATCH_FIELDS fields (the table rides in the kernel arguments);
+//   - with hgrad, y goes to library-owned scratch and a batched 7-point
+//     kernel writes z.
+// With STENCIL_PROGRAM_AUTOTUNE the compiled (tile_j, prefetch) variants of
+// the column kernel are timed once per program signature and the fastest is
+// kept.  With STENCIL_PROGRAM_GRAPH the launches are captured once per
+// signature into a hipGraph that later calls replay.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
 #include "../../include/stencil.h"
+#include "launch.hpp"
 #include "program.hpp"
+#include "program_kernels.hpp"
 
 #define STENCIL_API extern "C" __attribute__((visibility("default")))
 
 namespace stl {
-int fail(int code, const char *fmt, ...);
-void program_release_all() {}
-}  // namespace stl
 
-STENCIL_API int stencil_program_run(const stencil_program_t *prog, void *stream) {
-    (void)prog;
-    (void)stream;
-    return stl::fail(STENCIL_E_UNSUPPORTED, "stencil_program_run: not available in this build");
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int check_field(const stencil_field_t *f, const char *name);
+int check_same(const stencil_field_t *const *fs, const char *const *names, int n);
+int check_halo(const stencil_field_t *f, const char *name, int need);
+size_t elem_size(int dtype);
+bool empty(const stencil_field_t *f);
+
+hipError_t launch_column_batch_f64(const ColumnBatch &, bool, int, int, int, int, hipStream_t);
+hipError_t launch_column_batch_f32(const ColumnBatch &, bool, int, int, int, int, hipStream_t);
+hipError_t launch_column_batch_bf16(const ColumnBatch &, bool, int, int, int, int, hipStream_t);
+hipError_t launch_hgrad_batch_f64(const HgradBatch &, int, hipStream_t);
+hipError_t launch_hgrad_batch_f32(const HgradBatch &, int, hipStream_t);
+hipError_t launch_hgrad_batch_bf16(const HgradBatch &, int, hipStream_t);
+bool batch_variant_f64(int, int);
+bool batch_variant_f32(int, int);
+bool batch_variant_bf16(int, int);
+
+#define TRY(x)                             \
+    do {                                   \
+        int rc_ = (x);                     \
+        if (rc_ != STENCIL_OK) return rc_; \
+    } while (0)
+
+namespace {
+
+struct Variant {
+    int tj, pf;
+};
+
+std::vector<Variant> variants_for(int dtype) {
+    std::vector<Variant> v;
+    const Variant all[] = {{2, 4}, {4, 4}, {2, 2}};
+    for (const Variant &c : all) {
+        const bool ok = dtype == STENCIL_F64   ? batch_variant_f64(c.tj, c.pf)
+                        : dtype == STENCIL_F32 ? batch_variant_f32(c.tj, c.pf)
+                                               : batch_variant_bf16(c.tj, c.pf);
+        if (ok) v.push_back(c);
+    }
+    return v;
 }
 
-STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *, const stencil_field_t *,
-                                           const stencil_field_t *, const stencil_field_t *,
-                                           const stencil_field_t *, const stencil_field_t *, double,
-                                           const stencil_field_t *, const stencil_field_t *,
-                                           const stencil_field_t *, const stencil_field_t *,
-                                           const stencil_config_t *, void *) {
-    return stl::fail(STENCIL_E_UNSUPPORTED, "stencil_hdiff_vadv_adjoint: not available in this build");
+int kh_bucket(int K) {
+    const int m = (K + 1) / 2;
+    return m <= 16 ? 16 : m <= 32 ? 32 : m <= 40 ? 40 : 48;
+}
+
+// One batched launch of the column stages, and of hgrad.
+struct ColumnLaunch {
+    ColumnBatch b;
+    int kh, ntiles, tj_nbj_rows;  // tj_nbj_rows: TJ the tile counts were computed for
+};
+
+// The planned program: everything a replay needs, pointers included.
+struct Plan {
+    int dtype = 0;
+    bool vdiff = false, hgrad = false;
+    std::vector<ColumnLaunch> col;
+    std::vector<HgradBatch> hg;
+    std::vector<int> hg_tiles;
+    size_t scratch_bytes = 0;
+};
+
+struct Entry {
+    Plan plan;
+    void *scratch = nullptr;
+    Variant var{0, 0};
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+std::mutex g_mu;
+std::map<uint64_t, std::unique_ptr<Entry>> g_cache;
+
+uint64_t fnv(uint64_t h, const void *p, size_t n) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t q = 0; q < n; ++q) {
+        h ^= c[q];
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+
+uint64_t signature(const stencil_program_t *prog, hipStream_t st) {
+    uint64_t h = 1469598103934665603ULL;
+    h = fnv(h, &prog->nsub, sizeof(prog->nsub));
+    h = fnv(h, &prog->stages, sizeof(prog->stages));
+    h = fnv(h, &prog->dt, sizeof(double) * 4);
+    h = fnv(h, &st, sizeof(st));
+    for (int s = 0; s < prog->nsub; ++s) {
+        const stencil_subdomain_t &sd = prog->sub[s];
+        h = fnv(h, &sd.coeff, sizeof(stencil_field_t) * 5);
+        h = fnv(h, &sd.nfields, sizeof(sd.nfields));
+        if (sd.nfields > 0) {
+            h = fnv(h, sd.u, sizeof(stencil_field_t) * sd.nfields);
+            h = fnv(h, sd.z, sizeof(stencil_field_t) * sd.nfields);
+        }
+    }
+    return h;
+}
+
+int check_program(const stencil_program_t *prog, int *dtype_out) {
+    if (!prog) return fail(STENCIL_E_NULL, "program is NULL");
+    if (prog->nsub < 0) return fail(STENCIL_E_ARG, "nsub < 0");
+    if (prog->nsub > 0 && !prog->sub) return fail(STENCIL_E_NULL, "program subdomains are NULL");
+    const int st = prog->stages;
+    const int chain1 = STENCIL_STAGE_HDIFF | STENCIL_STAGE_VADV;
+    const int chain2 = chain1 | STENCIL_STAGE_VDIFF;
+    const int chain3 = chain2 | STENCIL_STAGE_HGRAD;
+    if (st != chain1 && st != chain2 && st != chain3)
+        return fail(STENCIL_E_ARG, "stages must be HDIFF|VADV[|VDIFF[|HGRAD]] (got %d)", st);
+    if (prog->flags & ~(STENCIL_PROGRAM_GRAPH | STENCIL_PROGRAM_AUTOTUNE))
+        return fail(STENCIL_E_ARG, "unknown program flags %d", prog->flags);
+    if (!std::isfinite(prog->dt) || !std::isfinite(prog->kappa) || !std::isfinite(prog->beta_h) ||
+        !std::isfinite(prog->beta_v))
+        return fail(STENCIL_E_ARG, "program parameters must be finite");
+    const int e = (st & STENCIL_STAGE_HGRAD) ? 1 : 0;
+    int dtype = -1;
+    struct Range {
+        uintptr_t lo, hi;
+        bool out;
+    };
+    std::vector<Range> ranges;
+    for (int s = 0; s < prog->nsub; ++s) {
+        const stencil_subdomain_t &sd = prog->sub[s];
+        if (sd.nfields < 0) return fail(STENCIL_E_ARG, "subdomain %d: nfields < 0", s);
+        if (sd.nfields > 0 && (!sd.u || !sd.z))
+            return fail(STENCIL_E_NULL, "subdomain %d: field arrays are NULL", s);
+        std::vector<const stencil_field_t *> fs = {&sd.coeff, &sd.wcon, &sd.a, &sd.b, &sd.c};
+        std::vector<const char *> names = {"coeff", "wcon", "a", "b", "c"};
+        for (int f = 0; f < sd.nfields; ++f) {
+            fs.push_back(&sd.u[f]);
+            names.push_back("u");
+        }
+        for (int f = 0; f < sd.nfields; ++f) {
+            fs.push_back(&sd.z[f]);
+            names.push_back("z");
+        }
+        for (size_t q = 0; q < fs.size(); ++q) TRY(check_field(fs[q], names[q]));
+        TRY(check_same(fs.data(), names.data(), static_cast<int>(fs.size())));
+        if (dtype < 0) dtype = sd.coeff.dtype;
+        if (sd.coeff.dtype != dtype) return fail(STENCIL_E_DTYPE, "subdomains differ in dtype");
+        if (empty(&sd.coeff) || sd.nfields == 0) continue;
+        for (int q = 0; q < 5; ++q) TRY(check_halo(fs[q], names[q], e));
+        for (int f = 0; f < sd.nfields; ++f) TRY(check_halo(&sd.u[f], "u", 2 + e));
+        if (sd.coeff.nk > KMAX_COLUMN)
+            return fail(STENCIL_E_UNSUPPORTED, "program columns support nk <= %d", KMAX_COLUMN);
+        const long long es = static_cast<long long>(elem_size(dtype));
+        const long long span = (sd.coeff.ni + 5) + (sd.coeff.nj + 5) * sd.coeff.sj +
+                               (sd.coeff.nk - 1) * sd.coeff.sk + 1;
+        if (span * es >= 2147483647LL)
+            return fail(STENCIL_E_UNSUPPORTED, "subdomain %d: fields of 2 GiB or more", s);
+        for (size_t q = 0; q < fs.size(); ++q) {
+            const stencil_field_t *f = fs[q];
+            const long long lo = -f->hi - static_cast<long long>(f->hj) * f->sj;
+            const long long hi = (f->ni + f->hi - 1) + static_cast<long long>(f->nj + f->hj - 1) * f->sj +
+                                 static_cast<long long>(f->nk - 1) * f->sk;
+            const uintptr_t base = reinterpret_cast<uintptr_t>(f->origin);
+            ranges.push_back({base + static_cast<intptr_t>(lo * es), base + static_cast<intptr_t>((hi + 1) * es),
+                              q >= 5 + static_cast<size_t>(sd.nfields)});
+        }
+    }
+    for (size_t o = 0; o < ranges.size(); ++o) {
+        if (!ranges[o].out) continue;
+        for (size_t q = 0; q < ranges.size(); ++q)
+            if (q != o && ranges[o].lo < ranges[q].hi && ranges[q].lo < ranges[o].hi)
+                return fail(STENCIL_E_ALIAS, "a program output overlaps another field");
+    }
+    *dtype_out = dtype < 0 ? STENCIL_F32 : dtype;
+    return STENCIL_OK;
+}
+
+// ColumnArgs of a subdomain's column stages on its interior grown by e.
+ColumnArgs column_args_ext(const stencil_field_t &cf, const stencil_subdomain_t &sd, int e,
+                           double dt, int tj) {
+    const long long es = static_cast<long long>(elem_size(cf.dtype));
+    const long long shift = (e + e * cf.sj) * es;
+    auto sh = [&](const void *p) { return static_cast<const void *>(static_cast<const char *>(p) - shift); };
+    ColumnArgs a{};
+    a.coeff = sh(sd.coeff.origin);
+    a.wcon = sh(sd.wcon.origin);
+    a.a = sh(sd.a.origin);
+    a.b = sh(sd.b.origin);
+    a.c = sh(sd.c.origin);
+    a.I = cf.ni + 2 * e;
+    a.J = cf.nj + 2 * e;
+    a.K = cf.nk;
+    a.sj = static_cast<int>(cf.sj);
+    a.sk = static_cast<int>(cf.sk);
+    a.u_bytes = static_cast<uint32_t>(((a.I + 3) + (a.J + 3) * cf.sj + (a.K - 1) * cf.sk + 1) * es);
+    a.col_bytes = static_cast<uint32_t>(((a.I - 1) + (a.J - 1) * cf.sj + (a.K - 1) * cf.sk + 1) * es);
+    a.nbi = (a.I + 63) / 64;
+    a.nbj = (a.J + tj - 1) / tj;
+    a.dt = dt;
+    return a;
+}
+
+// Builds the launch tables for a given column-kernel tile height.  Scratch
+// offsets for y are laid out when `scratch` is null (sizing pass).
+int build_plan(const stencil_program_t *prog, int dtype, int tj, char *scratch, Plan *plan) {
+    plan->dtype = dtype;
+    plan->vdiff = (prog->stages & STENCIL_STAGE_VDIFF) != 0;
+    plan->hgrad = (prog->stages & STENCIL_STAGE_HGRAD) != 0;
+    plan->col.clear();
+    plan->hg.clear();
+    plan->hg_tiles.clear();
+    const int e = plan->hgrad ? 1 : 0;
+    const long long es = static_cast<long long>(elem_size(dtype));
+    size_t off = 0;
+    // Scratch y per (subdomain, field), same strides as the subdomain.
+    std::vector<std::vector<char *>> ys(prog->nsub);
+    for (int s = 0; s < prog->nsub; ++s) {
+        const stencil_subdomain_t &sd = prog->sub[s];
+        if (!plan->hgrad || empty(&sd.coeff) || sd.nfields == 0) continue;
+        for (int f = 0; f < sd.nfields; ++f) {
+            const size_t bytes = static_cast<size_t>((static_cast<long long>(sd.coeff.nk) * sd.coeff.sk +
+                                                      2 * (sd.coeff.sj + 1)) * es);
+            // origin one row and one column in, so the 1-cell ring is addressable
+            ys[s].push_back(scratch ? scratch + off + (sd.coeff.sj + 1) * es : nullptr);
+            off += (bytes + 255) / 256 * 256;
+        }
+    }
+    plan->scratch_bytes = off;
+
+    for (int bucket : {16, 32, 40, 48}) {
+        ColumnLaunch cl{};
+        cl.kh = bucket;
+        cl.tj_nbj_rows = tj;
+        int tiles = 0;
+        auto flush = [&]() {
+            if (cl.b.nsub > 0) {
+                cl.ntiles = tiles;
+                cl.b.kappa = prog->kappa;
+                plan->col.push_back(cl);
+            }
+            cl.b = ColumnBatch{};
+            tiles = 0;
+        };
+        cl.b = ColumnBatch{};
+        for (int s = 0; s < prog->nsub; ++s) {
+            const stencil_subdomain_t &sd = prog->sub[s];
+            if (empty(&sd.coeff) || sd.nfields == 0 || kh_bucket(sd.coeff.nk) != bucket) continue;
+            const ColumnArgs a = column_args_ext(sd.coeff, sd, e, prog->dt, tj);
+            const long long shift = (e + e * sd.coeff.sj) * es;
+            for (int f0 = 0; f0 < sd.nfields; f0 += BATCH_FIELDS) {
+                if (cl.b.nsub == BATCH_SUBS) flush();
+                ColumnBatchSub &sb = cl.b.sub[cl.b.nsub++];
+                sb.a = a;
+                sb.nfields = sd.nfields - f0 < BATCH_FIELDS ? sd.nfields - f0 : BATCH_FIELDS;
+                sb.tile0 = tiles;
+                for (int f = 0; f < sb.nfields; ++f) {
+                    // u addressed from cell (-2, -2) of the grown domain
+                    sb.u[f] = static_cast<const char *>(sd.u[f0 + f].origin) - shift - (2 + 2 * sd.coeff.sj) * es;
+                    void *out = plan->hgrad ? static_cast<void *>(ys[s][f0 + f]) : sd.z[f0 + f].origin;
+                    sb.x[f] = out ? static_cast<char *>(out) - shift : nullptr;
+                }
+                tiles += a.nbi * a.nbj * sb.nfields;
+            }
+        }
+        flush();
+    }
+    if (plan->hgrad) {
+        HgradBatch hb{};
+        int tiles = 0;
+        auto flush = [&]() {
+            if (hb.nsub > 0) {
+                hb.beta_h = prog->beta_h;
+                hb.beta_v = prog->beta_v;
+                plan->hg.push_back(hb);
+                plan->hg_tiles.push_back(tiles);
+            }
+            hb = HgradBatch{};
+            tiles = 0;
+        };
+        for (int s = 0; s < prog->nsub; ++s) {
+            const stencil_subdomain_t &sd = prog->sub[s];
+            if (empty(&sd.coeff) || sd.nfields == 0) continue;
+            const stencil_field_t &cf = sd.coeff;
+            for (int f0 = 0; f0 < sd.nfields; f0 += BATCH_FIELDS) {
+                if (hb.nsub == BATCH_SUBS) flush();
+                HgradSub &h = hb.sub[hb.nsub++];
+                h.I = cf.ni; h.J = cf.nj; h.K = cf.nk;
+                h.sj = static_cast<int>(cf.sj); h.sk = static_cast<int>(cf.sk);
+                h.nbi = (cf.ni + 63) / 64;
+                h.nbj = (cf.nj + 3) / 4;
+                h.nfields = sd.nfields - f0 < BATCH_FIELDS ? sd.nfields - f0 : BATCH_FIELDS;
+                h.tile0 = tiles;
+                h.y_bytes = static_cast<uint32_t>(((cf.ni + 1) + (cf.nj + 1) * cf.sj + (cf.nk - 1) * cf.sk + 1) * es);
+                h.z_bytes = static_cast<uint32_t>(((cf.ni - 1) + (cf.nj - 1) * cf.sj + (cf.nk - 1) * cf.sk + 1) * es);
+                for (int f = 0; f < h.nfields; ++f) {
+                    h.y[f] = ys[s][f0 + f];
+                    h.z[f] = sd.z[f0 + f].origin;
+                }
+                tiles += h.nbi * h.nbj * h.nfields;
+            }
+        }
+        flush();
+    }
+    return STENCIL_OK;
+}
+
+hipError_t enqueue(const Plan &plan, Variant v, hipStream_t st, bool columns_only = false) {
+    for (const ColumnLaunch &cl : plan.col) {
+        hipError_t e;
+        switch (plan.dtype) {
+        case STENCIL_F64: e = launch_column_batch_f64(cl.b, plan.vdiff, cl.kh, v.tj, v.pf, cl.ntiles, st); break;
+        case STENCIL_F32: e = launch_column_batch_f32(cl.b, plan.vdiff, cl.kh, v.tj, v.pf, cl.ntiles, st); break;
+        default: e = launch_column_batch_bf16(cl.b, plan.vdiff, cl.kh, v.tj, v.pf, cl.ntiles, st); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    if (columns_only) return hipSuccess;
+    for (size_t q = 0; q < plan.hg.size(); ++q) {
+        hipError_t e;
+        switch (plan.dtype) {
+        case STENCIL_F64: e = launch_hgrad_batch_f64(plan.hg[q], plan.hg_tiles[q], st); break;
+        case STENCIL_F32: e = launch_hgrad_batch_f32(plan.hg[q], plan.hg_tiles[q], st); break;
+        default: e = launch_hgrad_batch_bf16(plan.hg[q], plan.hg_tiles[q], st); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Times the column launches of each compiled variant (3 runs after a warm-up).
+int autotune(const stencil_program_t *prog, int dtype, char *scratch, hipStream_t st, Variant *best) {
+    const std::vector<Variant> cands = variants_for(dtype);
+    float best_ms = 1e30f;
+    *best = cands.front();
+    hipEvent_t e0, e1;
+    hipError_t he = hipEventCreate(&e0);
+    if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
+    he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        hipEventDestroy(e0);
+        return hip_fail(he, "hipEventCreate");
+    }
+    int rc = STENCIL_OK;
+    for (const Variant &v : cands) {
+        Plan p;
+        build_plan(prog, dtype, v.tj, scratch, &p);
+        hipError_t e = enqueue(p, v, st, true);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = enqueue(p, v, st, true);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune");
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            *best = v;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+}
+
+}  // namespace
+
+void program_release_all() {
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (!g_cache.empty()) hipDeviceSynchronize();
+    for (auto &kv : g_cache) {
+        Entry &en = *kv.second;
+        if (en.exec) hipGraphExecDestroy(en.exec);
+        if (en.graph) hipGraphDestroy(en.graph);
+        if (en.scratch) hipFree(en.scratch);
+    }
+    g_cache.clear();
+}
+
+}  // namespace stl
+
+using namespace stl;
+
+STENCIL_API int stencil_program_run(const stencil_program_t *prog, void *stream) {
+    int dtype = 0;
+    TRY(check_program(prog, &dtype));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // Capture needs a real stream; on the null stream the program runs eagerly.
+    const bool graph = (prog->flags & STENCIL_PROGRAM_GRAPH) && st != nullptr;
+    const bool tune = (prog->flags & STENCIL_PROGRAM_AUTOTUNE) != 0;
+    const uint64_t key = signature(prog, st);
+
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_cache.find(key);
+    if (it == g_cache.end()) {
+        std::unique_ptr<Entry> en(new Entry);
+        Plan sizing;
+        build_plan(prog, dtype, 2, nullptr, &sizing);
+        if (sizing.scratch_bytes) {
+            hipError_t e = hipMalloc(&en->scratch, sizing.scratch_bytes);
+            if (e != hipSuccess) return hip_fail(e, "hipMalloc(program scratch)");
+        }
+        const std::vector<Variant> cands = variants_for(dtype);
+        en->var = cands.front();
+        if (tune && cands.size() > 1) {
+            const int rc = autotune(prog, dtype, static_cast<char *>(en->scratch), st, &en->var);
+            if (rc != STENCIL_OK) {
+                if (en->scratch) hipFree(en->scratch);
+                return rc;
+            }
+        }
+        build_plan(prog, dtype, en->var.tj, static_cast<char *>(en->scratch), &en->plan);
+        it = g_cache.emplace(key, std::move(en)).first;
+    }
+    Entry &en = *it->second;
+    if (!graph) {
+        const hipError_t e = enqueue(en.plan, en.var, st);
+        return e == hipSuccess ? STENCIL_OK : hip_fail(e, "program kernels");
+    }
+    if (!en.exec) {
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        const hipError_t le = enqueue(en.plan, en.var, st);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(st, &g);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return hip_fail(le != hipSuccess ? le : e, "graph capture");
+        }
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        en.graph = g;
+        en.exec = x;
+    }
+    const hipError_t e = hipGraphLaunch(en.exec, st);
+    return e == hipSuccess ? STENCIL_OK : hip_fail(e, "hipGraphLaunch");
 }

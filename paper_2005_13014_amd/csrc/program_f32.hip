@@ -1,0 +1,39 @@
+// Batched timestep kernels instantiated for float storage.
+#include "launch.hpp"
+#include "program_kernels.hpp"
+
+namespace stl {
+
+template <bool VDIFF, int TJ, int PF>
+static hipError_t by_levels(const ColumnBatch &b, int kh, int ntiles, hipStream_t st) {
+    switch (kh) {
+    case 16: return launch_column_batch_t<float, VDIFF, TJ, PF, 16, 2>(b, ntiles, st);
+    case 32: return launch_column_batch_t<float, VDIFF, TJ, PF, 32, 2>(b, ntiles, st);
+    case 40: return launch_column_batch_t<float, VDIFF, TJ, PF, 40, 2>(b, ntiles, st);
+    case 48: return launch_column_batch_t<float, VDIFF, TJ, PF, 48, 1>(b, ntiles, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+bool batch_variant_f32(int tile_j, int prefetch) {
+    if (tile_j == 2 && prefetch == 4) return true;
+    if (tile_j == 4 && prefetch == 4) return true;
+    return false;
+}
+
+hipError_t launch_column_batch_f32(const ColumnBatch &b, bool vdiff, int kh, int tile_j,
+                                   int prefetch, int ntiles, hipStream_t st) {
+    if (tile_j == 2 && prefetch == 4)
+        return vdiff ? by_levels<true, 2, 4>(b, kh, ntiles, st)
+                     : by_levels<false, 2, 4>(b, kh, ntiles, st);
+    if (tile_j == 4 && prefetch == 4)
+        return vdiff ? by_levels<true, 4, 4>(b, kh, ntiles, st)
+                     : by_levels<false, 4, 4>(b, kh, ntiles, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_hgrad_batch_f32(const HgradBatch &b, int ntiles, hipStream_t st) {
+    return launch_hgrad_batch_t<float>(b, ntiles, st);
+}
+
+}  // namespace stl

@@ -1,0 +1,35 @@
+// Batched timestep kernels instantiated for double storage.
+#include "launch.hpp"
+#include "program_kernels.hpp"
+
+namespace stl {
+
+template <bool VDIFF, int TJ, int PF>
+static hipError_t by_levels(const ColumnBatch &b, int kh, int ntiles, hipStream_t st) {
+    switch (kh) {
+    case 16: return launch_column_batch_t<double, VDIFF, TJ, PF, 16, 2>(b, ntiles, st);
+    case 32: return launch_column_batch_t<double, VDIFF, TJ, PF, 32, 1>(b, ntiles, st);
+    case 40: return launch_column_batch_t<double, VDIFF, TJ, PF, 40, 1>(b, ntiles, st);
+    case 48: return launch_column_batch_t<double, VDIFF, TJ, PF, 48, 1>(b, ntiles, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+bool batch_variant_f64(int tile_j, int prefetch) {
+    if (tile_j == 2 && prefetch == 2) return true;
+    return false;
+}
+
+hipError_t launch_column_batch_f64(const ColumnBatch &b, bool vdiff, int kh, int tile_j,
+                                   int prefetch, int ntiles, hipStream_t st) {
+    if (tile_j == 2 && prefetch == 2)
+        return vdiff ? by_levels<true, 2, 2>(b, kh, ntiles, st)
+                     : by_levels<false, 2, 2>(b, kh, ntiles, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_hgrad_batch_f64(const HgradBatch &b, int ntiles, hipStream_t st) {
+    return launch_hgrad_batch_t<double>(b, ntiles, st);
+}
+
+}  // namespace stl

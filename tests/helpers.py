@@ -46,3 +46,32 @@ def halo_untouched(field, canary=-7.0):
     mask = np.ones(p.shape, bool)
     mask[:, field.hj:field.hj + field.nj, field.hi:field.hi + field.ni] = False
     return bool(np.all(p[mask] == canary))
+
+
+def limiter_masks(u_padded, h, storage):
+    """Keep masks (1 = flux kept) of the limiter evaluated in the kernels'
+    arithmetic for `storage`: float32 for f32/bf16, float64 for f64.  The
+    Laplacian and the fluxes are formed in the order the operator defines,
+    which single float32 operations reproduce exactly.  Returns (kx, ky) as
+    uint8 arrays with halo 1 in the oracle's flux layout."""
+    ft = np.float64 if storage == "f64" else np.float32
+    u = u_padded.astype(ft)
+    nk, pj, pi = u.shape
+    ni, nj = pi - 2 * h, pj - 2 * h
+
+    def U(di, dj):  # u shifted, on the lap domain [-1, ni] x [-1, nj]
+        return u[:, h - 1 + dj:h + nj + 1 + dj, h - 1 + di:h + ni + 1 + di]
+
+    four = ft(4)
+    lap = four * U(0, 0) - U(1, 0) - U(-1, 0) - U(0, 1) - U(0, -1)   # index [k, j+1, i+1]
+    uc = U(0, 0)
+    kx = np.zeros((nk, nj + 2, ni + 2), np.uint8)
+    ky = np.zeros((nk, nj + 2, ni + 2), np.uint8)
+    # x faces i in [-1, ni-1], j in [0, nj)
+    f = lap[:, 1:nj + 1, 1:ni + 2] - lap[:, 1:nj + 1, 0:ni + 1]
+    du = uc[:, 1:nj + 1, 1:ni + 2] - uc[:, 1:nj + 1, 0:ni + 1]
+    kx[:, 1:nj + 1, 0:ni + 1] = ~(f * du > 0)
+    f = lap[:, 1:nj + 2, 1:ni + 1] - lap[:, 0:nj + 1, 1:ni + 1]
+    du = uc[:, 1:nj + 2, 1:ni + 1] - uc[:, 0:nj + 1, 1:ni + 1]
+    ky[:, 0:nj + 1, 1:ni + 1] = ~(f * du > 0)
+    return kx, ky

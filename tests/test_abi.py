@@ -167,3 +167,49 @@ def test_probe_copy_validation():
     assert lib.stencil_probe_copy(None, ctypes.c_void_p(FAKE), 16, None) == 1
     assert lib.stencil_probe_copy(ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE + 1024), 17, None) == 9
     assert lib.stencil_probe_copy(ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE + 16), 64, None) == 6
+
+
+# ---- batched program validation --------------------------------------------
+
+FULL = 1 | 2 | 4 | 8
+
+
+def program(halo_u=3, halo_c=1, stages=FULL, nsub=1, alias=False, nfields=2):
+    keep = []
+    subs = (B.Subdomain * max(1, nsub))()
+    base = FAKE
+    for s in range(nsub):
+        def nxt(h):
+            nonlocal base
+            base += 1 << 30
+            return fd(origin=base, hi=h, hj=h, sj=40, sk=40 * 40)
+        coef = [nxt(halo_c) for _ in range(5)]
+        us = (B.FieldDesc * nfields)(*[nxt(halo_u) for _ in range(nfields)])
+        zs = (B.FieldDesc * nfields)(*[nxt(0) for _ in range(nfields)])
+        if alias:
+            zs[1].origin = us[0].origin
+        keep += [us, zs]
+        subs[s] = B.Subdomain(*coef, nfields, us, zs)
+    keep.append(subs)
+    return B.Program(nsub, subs, stages, 0, 10.0, 0.1, 0.05, 0.01), keep
+
+
+def run_program(p):
+    return B.lib().stencil_program_run(ctypes.byref(p), None)
+
+
+def test_program_validation():
+    assert B.lib().stencil_program_run(None, None) == 1
+    p, keep = program(stages=1 | 4)
+    assert run_program(p) == 9
+    p, keep = program(halo_u=2)                      # hgrad grows the domain: u needs 3
+    assert run_program(p) == 5
+    p, keep = program(halo_c=0)                      # coefficients need the 1-cell ring
+    assert run_program(p) == 5
+    p, keep = program(alias=True)
+    assert run_program(p) == 6
+    p, keep = program()
+    p.dt = float("nan")
+    assert run_program(p) == 9
+    p, keep = program(nsub=0)
+    assert run_program(p) == 0                       # an empty program is a no-op

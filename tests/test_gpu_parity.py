@@ -141,7 +141,7 @@ def test_config3_full_size(dtype, n):
     assert halo_untouched(x)
 
 
-@pytest.mark.parametrize("tj,pf", [(4, 4), (4, 2), (4, 8), (2, 4), (1, 8)])
+@pytest.mark.parametrize("tj,pf", [(2, 4), (4, 4), (2, 2), (2, 8), (1, 4)])
 def test_fused_variants_are_bitwise_identical(tj, pf):
     ni, nj, nk = 200, 37, 80
     f = inputs.fields(ni, nj, nk, 2, seed=SEED + 4, storage="f32")

@@ -1,0 +1,150 @@
+"""The batched timestep program on the GPU: every stage prefix against the
+oracle, the 6-subdomain x 8-field configuration, graph replay, autotuning
+and table chunking (GPU only)."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import DT, TOL, normwise
+from paper_2005_13014_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2005_13014_amd import binding as B  # noqa: E402
+
+KAPPA, BH, BV = 0.1, 0.05, 0.01
+FULL = B.STAGE_HDIFF | B.STAGE_VADV | B.STAGE_VDIFF | B.STAGE_HGRAD
+
+
+def note(*a):
+    print(*a, flush=True)
+
+
+def device_program(data, dtype, canary=-7.0):
+    subs = []
+    for d in data:
+        h = d["halo"]
+        s = {n: B.Field.from_numpy(d[n], h, dtype) for n in ("coeff", "wcon", "a", "b", "c")}
+        s["u"] = [B.Field.from_numpy(u, h, dtype) for u in d["u"]]
+        ni, nj, nk = d["shape"]
+        s["z"] = [B.Field.empty(ni, nj, nk, h, dtype, fill=canary) for _ in d["u"]]
+        subs.append(s)
+    return subs
+
+
+def reference(d, f, stages):
+    h = d["halo"]
+    args = (d["u"][f], h, d["coeff"], h, d["wcon"], h, d["a"], h, d["b"], h, d["c"], h, DT)
+    if stages == FULL:
+        return oracle.timestep(*args, KAPPA, BH, BV)
+    x = oracle.hdiff_vadv(*args)
+    if stages & B.STAGE_VDIFF:
+        x = oracle.vdiff(x, 0, KAPPA)
+    return x
+
+
+def run(subs, stages, flags=0):
+    spec = B.ProgramSpec(subs, stages=stages, dt=DT, kappa=KAPPA, beta_h=BH, beta_v=BV, flags=flags)
+    B.stencil_program_run(spec)
+    torch.cuda.synchronize()
+
+
+def small_data(dtype, nfields=3, shapes=((70, 13, 9), (40, 33, 17), (5, 3, 1), (64, 8, 40))):
+    return inputs.batched(storage=dtype, subdomains=shapes, nfields=nfields)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("stages", [B.STAGE_HDIFF | B.STAGE_VADV,
+                                    B.STAGE_HDIFF | B.STAGE_VADV | B.STAGE_VDIFF, FULL])
+def test_program_stage_chains(dtype, stages):
+    data = small_data(dtype)
+    subs = device_program(data, dtype)
+    run(subs, stages)
+    worst = 0.0
+    for d, s in zip(data, subs):
+        for f in range(len(d["u"])):
+            got = s["z"][f].to_numpy(interior=True)
+            worst = max(worst, normwise(got, reference(d, f, stages)))
+    note("program %s stages %d worst normwise %.2e" % (dtype, stages, worst))
+    # z is rounded once more per intermediate kept in storage precision.
+    tol = {"f64": 1e-12, "f32": 1e-5, "bf16": 2.0 ** -7}[dtype]
+    assert worst <= tol
+
+
+def test_config4_six_subdomains_eight_fields():
+    """hdiff -> vadv -> vdiff -> hgrad on 8 fields over the 6 uneven
+    subdomains (96x96x60 .. 384x256x90), FP32, graph + autotune."""
+    data = inputs.batched(storage="f32")
+    subs = device_program(data, "f32")
+    run(subs, FULL, flags=B.PROGRAM_GRAPH | B.PROGRAM_AUTOTUNE)
+    worst = 0.0
+    for s_idx, (d, s) in enumerate(zip(data, subs)):
+        fields = range(8) if s_idx < 4 else (0, 7)
+        for f in fields:
+            got = s["z"][f].to_numpy(interior=True)
+            e = normwise(got, reference(d, f, FULL))
+            worst = max(worst, e)
+    note("C4 worst normwise %.2e" % worst)
+    assert worst <= TOL["f32"]
+
+
+def test_graph_replays_match_eager():
+    data = small_data("f32")
+    subs = device_program(data, "f32")
+    run(subs, FULL)
+    eager = [[z.to_numpy() for z in s["z"]] for s in subs]
+    spec = B.ProgramSpec(subs, stages=FULL, dt=DT, kappa=KAPPA, beta_h=BH, beta_v=BV,
+                         flags=B.PROGRAM_GRAPH)
+    for rep in range(4):
+        for s in subs:
+            for z in s["z"]:
+                z.buf.fill_(-7.0)
+        # eager work of the program's own between replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        B.stencil_program_run(spec)
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for s, ref in zip(subs, eager):
+            for z, r in zip(s["z"], ref):
+                assert np.array_equal(z.to_numpy(), r), rep
+
+
+def test_autotune_does_not_change_results():
+    data = small_data("f32", nfields=2)
+    subs = device_program(data, "f32")
+    run(subs, FULL)
+    ref = [[z.to_numpy() for z in s["z"]] for s in subs]
+    run(subs, FULL, flags=B.PROGRAM_AUTOTUNE)
+    for s, r in zip(subs, ref):
+        for z, rr in zip(s["z"], r):
+            assert np.array_equal(z.to_numpy(), rr)
+
+
+def test_tables_split_over_many_subdomains_and_fields():
+    # 10 subdomains (more than one table) and 11 fields (more than one entry).
+    shapes = tuple((17 + 3 * q, 6 + q, 5 + q) for q in range(10))
+    data = inputs.batched(storage="f32", subdomains=shapes, nfields=11, halo_u=3, halo_coef=3)
+    data[3]["u"] = data[3]["u"][:0]  # a subdomain without fields
+    subs = device_program(data, "f32")
+    run(subs, FULL)
+    worst = 0.0
+    for d, s in zip(data, subs):
+        for f in range(len(d["u"])):
+            worst = max(worst, normwise(s["z"][f].to_numpy(interior=True), reference(d, f, FULL)))
+    assert worst <= TOL["f32"]
+
+
+def test_program_outputs_leave_halos_alone():
+    data = small_data("f32", nfields=1)
+    subs = device_program(data, "f32")
+    run(subs, FULL)
+    for s in subs:
+        p = s["z"][0].to_numpy()
+        h = s["z"][0].hi
+        mask = np.ones(p.shape, bool)
+        mask[:, h:-h, h:-h] = False
+        assert np.all(p[mask] == -7.0)
