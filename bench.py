@@ -2,16 +2,20 @@
 
 One step = one call of the fused program (Laplacian -> limited fluxes ->
 update -> flux-form right-hand side -> Thomas elimination and
-back-substitution) over a 512 x 512 x 80 grid with FP32 storage and
+back-substitution) over a 512 x 512 x 80 grid with FP32 storage and stencil
 arithmetic and the FP64 Thomas solve, inputs resident in HBM.  Several input
 sets are rotated so that no step finds its inputs in the 256 MB Infinity
 Cache left by the previous one.
 
-Prints ONE JSON line on stdout; progress goes to stderr.
+Prints ONE JSON line on stdout; progress goes to stderr.  Beside the headline
+it reports the FP64 and bf16 variants, the unfused "original" FP64 path, the
+hdiff optimisation levels, the batched timestep, the adjoint, the copy-probe
+ceiling and the CPU oracle on the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -27,19 +31,46 @@ METRIC = "fused hdiff+vadv Gpoints/s & % peak HBM GB/s, FP32 vs FP64 at stated e
 PEAK_HBM_GBS = 8000.0
 DT = 10.0
 SEED = 200513014
+ES = {"f32": 4, "f64": 8, "bf16": 2}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_column_f32_512x512x80.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_13014_amd", "csrc", n)
+                  for n in ("column.hpp", "common.hpp", "column_f32.hip")]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(ni, nj, nk, es, fields_in=6, fields_out=1):
-    """Bytes a fused call must move: u over the interior plus the part of its
-    2-cell ring the 13-point diamond reaches (ni nj + 4 (ni + nj) + 4 cells per
-    level), the other inputs and the output on the interior."""
-    u_cells = (ni * nj + 4 * (ni + nj) + 4) * nk
-    other = (fields_in - 1 + fields_out) * ni * nj * nk
-    return es * (u_cells + other)
+def u_cells(ni, nj, nk):
+    """Cells of u a fused call must read: the interior plus the part of its
+    2-cell ring that the 13-point diamond reaches."""
+    return (ni * nj + 4 * (ni + nj) + 4) * nk
+
+
+def fused_bytes(ni, nj, nk, es):
+    """Algorithmic bytes of one fused call: u, five more inputs and the output."""
+    return es * (u_cells(ni, nj, nk) + 6 * ni * nj * nk)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary, or None if it is missing or was taken for other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sources_sha256_16") != kernel_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
 
 
 def make_set(ni, nj, nk, dtype, seed):
@@ -51,43 +82,150 @@ def make_set(ni, nj, nk, dtype, seed):
     return f, g
 
 
-def run_call(g, cfg=None):
-    from paper_2005_13014_amd import binding as B
-    B.stencil_hdiff_vadv(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT, g["x"], cfg=cfg)
+def n_sets_for(nbytes):
+    return max(2, min(8, math.ceil(3 * 256e6 / nbytes) + 1))
 
 
-def time_calls(sets, steps, warmup, cfg=None):
-    """Returns (wall ms per step, mean kernel ms from HIP events, list of ms)."""
+def time_calls(fn, sets, steps, warmup):
+    """Runs fn(set) over rotating sets.  Returns (wall ms per step, mean ms of
+    one call from HIP events on the current stream)."""
     import torch
     stream = torch.cuda.current_stream()
     for s in range(warmup):
-        run_call(sets[s % len(sets)], cfg)
+        fn(sets[s % len(sets)])
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
     t0 = time.perf_counter()
     for s in range(steps):
         ev[s][0].record(stream)
-        run_call(sets[s % len(sets)], cfg)
+        fn(sets[s % len(sets)])
         ev[s][1].record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
-    ms = [a.elapsed_time(b) for a, b in ev]
-    return wall, float(np.mean(ms)), ms
+    return wall, float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
 
-def errors(f, g):
+def fused(cfg=None):
+    from paper_2005_13014_amd import binding as B
+
+    def fn(g):
+        B.stencil_hdiff_vadv(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT, g["x"],
+                             cfg=cfg)
+    return fn
+
+
+def errors(f, x):
     import oracle
     ref = oracle.hdiff_vadv(f["u"], 2, f["coeff"], 2, f["wcon"], 2, f["a"], 2, f["b"], 2, f["c"], 2,
                             DT)
-    got = g["x"].to_numpy(interior=True)
+    got = x.to_numpy(interior=True)
     return {"normwise": float(np.abs(got - ref).max() / np.abs(ref).max()),
             "rms": float(np.sqrt(np.mean((got - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))}
 
 
-def n_sets_for(ni, nj, nk, es):
-    foot = algorithmic_bytes(ni, nj, nk, es)
-    return max(2, min(8, math.ceil(3 * 256e6 / foot) + 1))
+def copy_probe():
+    import torch
+    from paper_2005_13014_amd import binding as B
+    nb = 1 << 30
+    src = torch.empty(nb // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        B.stencil_probe_copy(src, dst, nb)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        B.stencil_probe_copy(src, dst, nb)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2 * nb / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+
+
+def variant_column(ni, nj, nk, dtype, level):
+    """Fused (level 0) or unfused 'original' (level 1) program in dtype."""
+    import torch
+    from paper_2005_13014_amd import binding as B
+    es = ES[dtype]
+    sets = [make_set(ni, nj, nk, dtype, SEED + 3 + 1000 * q)
+            for q in range(n_sets_for(fused_bytes(ni, nj, nk, es)))]
+    cfg = B.config(level=level)
+    w, k = time_calls(fused(cfg), [s[1] for s in sets], 20, 3)
+    fused(cfg)(sets[0][1])
+    torch.cuda.synchronize()
+    ab = fused_bytes(ni, nj, nk, es)
+    out = {"Gpoints_s": ni * nj * nk / (w * 1e-3) / 1e9, "ms": w,
+           "algorithmic_GBs": ab / (k * 1e-3) / 1e9,
+           "frac_hbm_peak": ab / (k * 1e-3) / 1e9 / PEAK_HBM_GBS,
+           "error_vs_fp64_oracle": errors(sets[0][0], sets[0][1]["x"])}
+    return out
+
+
+def variant_hdiff_levels(ni, nj, nk):
+    """hdiff alone in FP32 at the paper's optimisation levels (Sec. VII-C)."""
+    from paper_2005_13014_amd import binding as B
+    from paper_2005_13014_amd import inputs
+    nb = 4 * (u_cells(ni, nj, nk) + 2 * ni * nj * nk)
+    sets = []
+    for q in range(n_sets_for(nb)):
+        f = inputs.fields(ni, nj, nk, 2, seed=SEED + 1 + q, storage="f32", vadv=False)
+        sets.append({"u": B.Field.from_numpy(f["u"], 2, "f32"),
+                     "coeff": B.Field.from_numpy(f["coeff"], 2, "f32"),
+                     "x": B.Field.empty(ni, nj, nk, 2, "f32", fill=0.0)})
+    out = {}
+    for label, cfg in (("original", B.config(level=1)), ("inline", B.config(unroll=1)),
+                       ("inline_unroll2", B.config(unroll=2)), ("inline_unroll4", B.config(unroll=4))):
+        def fn(g, cfg=cfg):
+            B.stencil_hdiff(g["u"], g["coeff"], g["x"], cfg=cfg)
+        w, k = time_calls(fn, sets, 20, 3)
+        out[label] = {"ms": w, "algorithmic_GBs": nb / (k * 1e-3) / 1e9}
+    return out
+
+
+def variant_program():
+    """The batched timestep: hdiff -> vadv -> vdiff -> hgrad on 8 fields over
+    6 uneven subdomains, FP32, hipGraph + autotuned variant."""
+    import torch
+    from paper_2005_13014_amd import binding as B
+    from paper_2005_13014_amd import inputs
+    data = inputs.batched(storage="f32")
+    subs = []
+    pts = 0
+    nbytes = 0
+    for d in data:
+        ni, nj, nk = d["shape"]
+        h = d["halo"]
+        s = {n: B.Field.from_numpy(d[n], h, "f32") for n in ("coeff", "wcon", "a", "b", "c")}
+        s["u"] = [B.Field.from_numpy(u, h, "f32") for u in d["u"]]
+        s["z"] = [B.Field.empty(ni, nj, nk, h, "f32", fill=0.0) for _ in d["u"]]
+        subs.append(s)
+        nf = len(d["u"])
+        pts += ni * nj * nk * nf
+        # per field: u (3-ring diamond of the grown domain ~ interior) + z; shared coefficients once
+        nbytes += 4 * (nf * 2 * ni * nj * nk + 5 * ni * nj * nk)
+    spec = B.ProgramSpec(subs, dt=DT, flags=B.PROGRAM_GRAPH | B.PROGRAM_AUTOTUNE)
+    w, k = time_calls(lambda _: B.stencil_program_run(spec), [None], 20, 3)
+    del subs
+    torch.cuda.empty_cache()
+    return {"ms": w, "Gfieldpoints_s": pts / (w * 1e-3) / 1e9,
+            "algorithmic_GBs_lower_bound": nbytes / (k * 1e-3) / 1e9, "field_points": pts}
+
+
+def variant_adjoint(n=256, nk=80):
+    from paper_2005_13014_amd import binding as B
+    from paper_2005_13014_amd import inputs
+    out = {}
+    for dtype in ("f32", "f64"):
+        f = inputs.fields(n, n, nk, 2, seed=SEED + 5, storage=dtype, loss=True)
+        g = {k: B.Field.from_numpy(f[k], 2, dtype) for k in ("u", "coeff", "wcon", "a", "b", "c", "w")}
+        gs = [g["u"].like(fill=0.0) for _ in range(3)]
+
+        def fn(_):
+            B.stencil_hdiff_vadv_adjoint(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT,
+                                         g["w"], *gs)
+        w, k = time_calls(fn, [None], 20, 3)
+        out[dtype] = {"ms": w, "Gpoints_s": n * n * nk / (w * 1e-3) / 1e9}
+    return out
 
 
 def cpu_baseline(ni, nj, nk, budget_s=10.0):
@@ -118,10 +256,12 @@ def main():
     ap.add_argument("--prefetch", type=int, default=0)
     ap.add_argument("--quick", action="store_true",
                     help="only the headline measurement (no variants, no CPU baseline)")
+    ap.add_argument("--with-copy", action="store_true",
+                    help="with --quick: also run the copy probe (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the stencil path runs on a single MI355X; "
-              "multi-GPU halo exchange is not built (pass --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the stencil path runs on a single MI355X and no "
+              "multi-GPU halo exchange is built; run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -132,22 +272,19 @@ def main():
 
     ni, nj, nk = args.size
     dtype = args.dtype
-    es = {"f32": 4, "f64": 8, "bf16": 2}[dtype]
+    es = ES[dtype]
     cfg = B.config(tile_j=args.tile_j, prefetch=args.prefetch)
-    nsets = n_sets_for(ni, nj, nk, es)
+    abytes = fused_bytes(ni, nj, nk, es)
+    nsets = n_sets_for(abytes)
     log("generating %d input sets %dx%dx%d %s" % (nsets, ni, nj, nk, dtype))
-    sets, host = [], None
-    for q in range(nsets):
-        f, g = make_set(ni, nj, nk, dtype, SEED + 3 + 1000 * q)
-        if q == 0:
-            host = f
-        sets.append(g)
+    sets = [make_set(ni, nj, nk, dtype, SEED + 3 + 1000 * q) for q in range(nsets)]
     log("timing %d steps after %d warmup" % (args.steps, args.warmup))
-    wall, kern, _ = time_calls(sets, args.steps, args.warmup, cfg)
+    wall, kern = time_calls(fused(cfg), [s[1] for s in sets], args.steps, args.warmup)
     pts = ni * nj * nk
-    abytes = algorithmic_bytes(ni, nj, nk, es)
     achieved = abytes / (kern * 1e-3) / 1e9
     log("wall %.4f ms/step, kernel %.4f ms, %.1f GB/s algorithmic" % (wall, kern, achieved))
+    headline = (ni, nj, nk, dtype) == (512, 512, 80, "f32") and not (args.tile_j or args.prefetch)
+    traffic = measured_traffic() if headline else None
 
     result = {
         "metric": METRIC,
@@ -166,57 +303,43 @@ def main():
         "config": {"workload": "fused hdiff+vadv %dx%dx%d halo 2, %s storage and stencil "
                                "arithmetic, FP64 Thomas solve" % (ni, nj, nk, dtype),
                    "ni": ni, "nj": nj, "nk": nk, "input_sets_rotated": nsets,
-                   "kernel": "k_hdiff_vadv"},
+                   "kernel": "k_column (fused)", "kernel_sources_sha256_16": kernel_hash()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic,
                      "algorithmic_bytes_per_launch": abytes, "kernel_ms": kern},
     }
-    if not args.quick:
-        log("checking errors against the oracle")
-        run_call(sets[0], cfg)
-        torch.cuda.synchronize()
-        result["error_vs_fp64_oracle"] = errors(host, sets[0])
-        variants = {}
-        # Copy ceiling from the bandwidth probe (1 GiB each way).
-        nb = 1 << 30
-        src = torch.empty(nb // 4, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            B.stencil_probe_copy(src, dst, nb)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(10):
-            B.stencil_probe_copy(src, dst, nb)
-        e1.record()
-        torch.cuda.synchronize()
-        variants["copy_probe_GBs"] = 2 * nb / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
-        del src, dst
-        # The unfused FP64 path ("original" level) on the same grid: the speedup denominator.
-        del sets
+    if args.quick:
+        if args.with_copy:
+            log("copy probe %.1f GB/s" % copy_probe())
+        print(json.dumps(result), flush=True)
+        return
+
+    log("checking errors against the oracle")
+    fused(cfg)(sets[0][1])
+    torch.cuda.synchronize()
+    result["error_vs_fp64_oracle"] = errors(sets[0][0], sets[0][1]["x"])
+    del sets
+    torch.cuda.empty_cache()
+    variants = {"copy_probe_GBs": copy_probe()}
+    torch.cuda.empty_cache()
+    for label, dt_, level in (("fused_f64", "f64", 0), ("original_f64", "f64", 1),
+                              ("fused_bf16", "bf16", 0)):
+        log("variant", label)
+        variants[label] = variant_column(ni, nj, nk, dt_, level)
         torch.cuda.empty_cache()
-        log("unfused fp64 and fused fp64 / bf16 variants")
-        for label, dt_, level in (("fused_f64", "f64", 0), ("original_f64", "f64", 1),
-                                  ("fused_bf16", "bf16", 0)):
-            es_ = {"f32": 4, "f64": 8, "bf16": 2}[dt_]
-            n_ = n_sets_for(ni, nj, nk, es_)
-            vs = [make_set(ni, nj, nk, dt_, SEED + 3 + 1000 * q) for q in range(n_)]
-            w_, k_, _ = time_calls([v[1] for v in vs], 20, 3, B.config(level=level))
-            run_call(vs[0][1], B.config(level=level))
-            torch.cuda.synchronize()
-            err = errors(vs[0][0], vs[0][1])
-            ab = algorithmic_bytes(ni, nj, nk, es_)
-            variants[label] = {"Gpoints_s": pts / (w_ * 1e-3) / 1e9, "ms": w_,
-                               "algorithmic_GBs": ab / (k_ * 1e-3) / 1e9,
-                               "frac_hbm_peak": ab / (k_ * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                               "error_vs_fp64_oracle": err}
-            del vs
-            torch.cuda.empty_cache()
-        variants["speedup_fused_f32_over_original_f64"] = (
-            variants["original_f64"]["ms"] / wall)
-        result["variants"] = variants
-        log("cpu baseline (oracle)")
-        result["cpu_baseline"] = cpu_baseline(ni, nj, nk)
+    variants["speedup_fused_f32_over_original_f64"] = variants["original_f64"]["ms"] / wall
+    log("variant hdiff optimisation levels")
+    variants["hdiff_f32_levels"] = variant_hdiff_levels(ni, nj, nk)
+    torch.cuda.empty_cache()
+    log("variant batched timestep")
+    variants["timestep_6x8_f32"] = variant_program()
+    torch.cuda.empty_cache()
+    log("variant adjoint 256x256x80")
+    variants["adjoint_256x256x80"] = variant_adjoint()
+    result["variants"] = variants
+    log("cpu baseline (oracle)")
+    result["cpu_baseline"] = cpu_baseline(ni, nj, nk)
     print(json.dumps(result), flush=True)
 
 

@@ -110,8 +110,12 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     __shared__ double2 xch[2 * NH];
 
     const int tid = threadIdx.x;
-    const int half = tid >= NH ? 1 : 0;
-    const int l = tid - half * NH, ti = l & 63, tj = l >> 6;
+    // Each half is a whole number of waves, so half and the wave's tile row
+    // are wave-uniform; readfirstlane lets the compiler keep them (and every
+    // per-level buffer offset derived from them) in scalar registers.
+    const int half = __builtin_amdgcn_readfirstlane(tid >= NH ? 1 : 0);
+    const int l = tid - half * NH, ti = l & 63;
+    const int tj = __builtin_amdgcn_readfirstlane(l >> 6);
     const int i0 = bi * TI, j0 = bj * TJ;
     const int gi = i0 + ti, gj = j0 + tj;
     const bool active = gi < p.I && gj < p.J;
@@ -123,9 +127,11 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     const auto ru = make_rsrc(p.u, FUSED ? p.u_bytes : p.col_bytes);
     const auto rcf = make_rsrc(p.coeff, p.col_bytes);
     const auto rw = make_rsrc(p.wcon, p.col_bytes);
-    const auto ra = make_rsrc(p.a, p.col_bytes);
+    // "lower" multiplies the neighbour already eliminated, "upper" the next:
+    // a and c for half 0, c and a for half 1 (swapped once here, not per level).
+    const auto rlo = make_rsrc(half ? p.c : p.a, p.col_bytes);
     const auto rb = make_rsrc(p.b, p.col_bytes);
-    const auto rc = make_rsrc(p.c, p.col_bytes);
+    const auto rup = make_rsrc(half ? p.a : p.c, p.col_bytes);
     const auto rx = make_rsrc(p.x, p.col_bytes);
 
     // u tile (fused): element (r, c) holds u(i0 - 2 + c, j0 - 2 + r).  Main block
@@ -154,7 +160,7 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     const int nsteps = half ? K - M : M;
     auto level = [&](int s) { return half ? K - 1 - s : s; };
 
-    C rum[PF][FUSED ? MR : 1], rus[PF], rcfv[PF], rwv[PF], rav[PF], rbv[PF], rcv[PF];
+    C rum[PF][FUSED ? MR : 1], rus[PF], rcfv[PF], rwv[PF], rlov[PF], rbv[PF], rupv[PF];
     auto load = [&](int q, int s) {
         const uint32_t so = static_cast<uint32_t>(level(s)) * sk_bytes;
         if constexpr (FUSED) {
@@ -166,15 +172,18 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
             rum[q][0] = IO::load(ru, vcol, so);
         }
         rwv[q] = IO::load(rw, vcol, so);
-        rav[q] = IO::load(ra, vcol, so);
+        rlov[q] = IO::load(rlo, vcol, so);
         rbv[q] = IO::load(rb, vcol, so);
-        rcv[q] = IO::load(rc, vcol, so);
+        rupv[q] = IO::load(rup, vcol, so);
     };
 #pragma unroll
     for (int q = 0; q < PF; ++q)
         if (q < nsteps) load(q, q);
 
-    const C dt = static_cast<C>(p.dt);
+    // d(prev) = h(prev) - dt (F above - F below).  Half 0 walks up (the new
+    // face is above the previous level), half 1 walks down (it is below), so
+    // d = h - dts (f_new - f_old) with dts = +dt or -dt (negation is exact).
+    const C dts = half ? -static_cast<C>(p.dt) : static_cast<C>(p.dt);
     C h_prev = C(0), w_prev = C(0), f_old = C(0);
     double lo_prev = 0.0, b_prev = 1.0, up_prev = 0.0;
     double P[KH], D[KH];
@@ -196,8 +205,8 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
             const C hv = FUSED ? C(0) : rum[q][0];
             const C cf = FUSED ? rcfv[q] : C(0);
             const C wv = rwv[q];
-            const double av = static_cast<double>(rav[q]), bv = static_cast<double>(rbv[q]),
-                         cv = static_cast<double>(rcv[q]);
+            const double lov = static_cast<double>(rlov[q]), bv = static_cast<double>(rbv[q]),
+                         upv = static_cast<double>(rupv[q]);
             if (s + PF < nsteps) load(q, s + PF);
             if constexpr (FUSED) __syncthreads();
             if (on) {
@@ -206,8 +215,7 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
                     // Face between the previous and this level; right-hand side
                     // and elimination of the previous level.
                     const C f_new = (C(0.5) * (w_prev + wv)) * (C(0.5) * (h_prev + h));
-                    const C diff = half ? (f_old - f_new) : (f_new - f_old);
-                    const double d = static_cast<double>(h_prev - dt * diff);
+                    const double d = static_cast<double>(h_prev - dts * (f_new - f_old));
                     const int tt = s > 0 ? s - 1 : 0;
                     if (tt == 0) {
                         const double r = recip(b_prev);
@@ -225,8 +233,8 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
                 }
                 h_prev = h;
                 w_prev = wv;
-                lo_prev = half ? cv : av;
-                up_prev = half ? av : cv;
+                lo_prev = lov;
+                up_prev = upv;
                 b_prev = bv;
             }
         }
@@ -241,8 +249,7 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
         f_mid = (C(0.5) * (w_prev + static_cast<C>(o1.y))) * (C(0.5) * (h_prev + static_cast<C>(o1.x)));
     double Pm = 0.0, Dm = 0.0;  // this half's eliminated interface row
     if (nsteps > 0) {
-        const C diff = half ? (f_old - f_mid) : (f_mid - f_old);
-        const double d = static_cast<double>(h_prev - dt * diff);
+        const double d = static_cast<double>(h_prev - dts * (f_mid - f_old));
         const double m = nsteps > 1 ? b_prev - lo_prev * P_last : b_prev;
         const double r = recip(m);
         Pm = up_prev * r;
