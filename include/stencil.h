@@ -95,6 +95,8 @@ typedef struct {
     int32_t unroll;   /* j-unroll factor of stencil_hdiff: 1, 2 or 4 (Sec. V-A) */
     int32_t tile_j;   /* rows of columns per workgroup: 1, 2 or 4 (fused kernels) */
     int32_t prefetch; /* k-levels loaded ahead of use: 2, 4 or 8 */
+    int32_t nontemporal; /* 1: read-once inputs and the output bypass cache
+                            retention (non-temporal loads and stores) */
 } stencil_config_t;
 
 /* Horizontal diffusion, per level k and interior point (i, j):

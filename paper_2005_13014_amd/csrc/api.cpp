@@ -212,20 +212,20 @@ static int run_plain(int dtype, PlainArgs a, hipStream_t st) {
     return launch_status(launch_plain(dtype, a, st), "unfused kernels");
 }
 
-static hipError_t launch_column(int dtype, bool fused, const ColumnArgs &a, int tj, int pf,
+static hipError_t launch_column(int dtype, bool fused, const ColumnArgs &a, int tj, int pf, bool nt,
                                 hipStream_t st) {
     switch (dtype) {
-    case STENCIL_F64: return launch_column_f64(fused, a, tj, pf, st);
-    case STENCIL_F32: return launch_column_f32(fused, a, tj, pf, st);
-    default: return launch_column_bf16(fused, a, tj, pf, st);
+    case STENCIL_F64: return launch_column_f64(fused, a, tj, pf, nt, st);
+    case STENCIL_F32: return launch_column_f32(fused, a, tj, pf, nt, st);
+    default: return launch_column_bf16(fused, a, tj, pf, nt, st);
     }
 }
 
-static bool column_variant(int dtype, int tj, int pf) {
+static bool column_variant(int dtype, int tj, int pf, bool nt) {
     switch (dtype) {
-    case STENCIL_F64: return column_variant_f64(tj, pf);
-    case STENCIL_F32: return column_variant_f32(tj, pf);
-    default: return column_variant_bf16(tj, pf);
+    case STENCIL_F64: return column_variant_f64(tj, pf, nt);
+    case STENCIL_F32: return column_variant_f32(tj, pf, nt);
+    default: return column_variant_bf16(tj, pf, nt);
     }
 }
 
@@ -336,7 +336,7 @@ STENCIL_API int stencil_vadv(const stencil_field_t *h, const stencil_field_t *wc
         return run_plain(dtype, p, st);
     }
     const ColumnArgs v = column_args(h, nullptr, wcon, a, b, c, x, dt, false);
-    return launch_status(launch_column(dtype, false, v, 0, 0, st), "vadv kernel");
+    return launch_status(launch_column(dtype, false, v, 0, 0, false, st), "vadv kernel");
 }
 
 STENCIL_API int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field_t *coeff,
@@ -355,8 +355,10 @@ STENCIL_API int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field
     const int dtype = u->dtype;
     const int tj = cf.tile_j ? cf.tile_j : 2;
     const int pf = cf.prefetch ? cf.prefetch : (dtype == STENCIL_F64 ? 2 : 4);
-    if (cf.level != STENCIL_LEVEL_ORIGINAL && !column_variant(dtype, tj, pf))
-        return fail(STENCIL_E_UNSUPPORTED, "no compiled fused variant tile_j=%d prefetch=%d", tj, pf);
+    const bool nt = cf.nontemporal != 0;
+    if (cf.level != STENCIL_LEVEL_ORIGINAL && !column_variant(dtype, tj, pf, nt))
+        return fail(STENCIL_E_UNSUPPORTED, "no compiled fused variant tile_j=%d prefetch=%d nontemporal=%d",
+                    tj, pf, cf.nontemporal);
     if (empty(u)) return STENCIL_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (cf.level == STENCIL_LEVEL_ORIGINAL || u->nk > KMAX_COLUMN || !column_fits(u)) {
@@ -374,7 +376,7 @@ STENCIL_API int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field
         return run_plain(dtype, p, st);
     }
     const ColumnArgs v = column_args(u, coeff, wcon, a, b, c, x, dt, true);
-    return launch_status(launch_column(dtype, true, v, tj, pf, st), "fused hdiff+vadv kernel");
+    return launch_status(launch_column(dtype, true, v, tj, pf, nt, st), "fused hdiff+vadv kernel");
 }
 
 STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stencil_field_t *coeff,

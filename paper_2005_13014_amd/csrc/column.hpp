@@ -47,37 +47,44 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
 
 template <class T> struct BufIO;
 
+// Cache policy operand of the buffer intrinsics: 0 = default, 2 = non-temporal.
 template <> struct BufIO<float> {
+    template <int CP = 0>
     static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, CP));
     }
+    template <int CP = 0>
     static __device__ __forceinline__ void store_d(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                                    double v) {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(static_cast<float>(v)), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(static_cast<float>(v)), r, vo, so, CP);
     }
 };
 
 template <> struct BufIO<double> {
+    template <int CP = 0>
     static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, CP));
     }
+    template <int CP = 0>
     static __device__ __forceinline__ void store_d(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                                    double v) {
         using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, vo, so, CP);
     }
 };
 
 template <> struct BufIO<uint16_t> {
+    template <int CP = 0>
     static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-        const uint32_t b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+        const uint32_t b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, CP);
         return __uint_as_float(b << 16);
     }
+    template <int CP = 0>
     static __device__ __forceinline__ void store_d(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                                    double v) {
         uint16_t b;
         Storage<uint16_t>::store_d(&b, v);
-        __builtin_amdgcn_raw_buffer_store_b16(b, r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(b, r, vo, so, CP);
     }
 };
 
@@ -97,11 +104,14 @@ __device__ __forceinline__ double recip(double m) {
 // One 64 x TJ tile of columns; VDIFF replaces x by y = x + kappa (x(k+1) -
 // 2 x(k) + x(k-1)) (zero flux through the bottom and top faces), finished
 // level by level during the back-substitution.
-template <class T, bool FUSED, bool VDIFF, int TJ, int PF, int KH>
+// NT: the read-once column inputs and the output use non-temporal accesses
+// (u is re-read by neighbouring tiles through L2 and keeps the default).
+template <class T, bool FUSED, bool VDIFF, int TJ, int PF, int KH, bool NT = false>
 __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj, double kappa) {
     using S = Storage<T>;
     using C = typename S::C;
     using IO = BufIO<T>;
+    constexpr int CP = NT ? 2 : 0;
     constexpr int TI = 64, PI = TI + 4, PJ = TJ + 4, MR = PJ / TJ, NH = 64 * TJ;
     static_assert(PJ % TJ == 0, "tile rows must split evenly over the lanes");
     constexpr int TILE = PJ * PI + 64;  // + one dummy slot per lane of the side-loading wave
@@ -167,14 +177,14 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
 #pragma unroll
             for (int m = 0; m < MR; ++m) rum[q][m] = IO::load(ru, vmain[m], so);
             if (side_wave) rus[q] = IO::load(ru, vside, so);
-            rcfv[q] = IO::load(rcf, vcol, so);
+            rcfv[q] = IO::template load<CP>(rcf, vcol, so);
         } else {
-            rum[q][0] = IO::load(ru, vcol, so);
+            rum[q][0] = IO::template load<CP>(ru, vcol, so);
         }
-        rwv[q] = IO::load(rw, vcol, so);
-        rlov[q] = IO::load(rlo, vcol, so);
-        rbv[q] = IO::load(rb, vcol, so);
-        rupv[q] = IO::load(rup, vcol, so);
+        rwv[q] = IO::template load<CP>(rw, vcol, so);
+        rlov[q] = IO::template load<CP>(rlo, vcol, so);
+        rbv[q] = IO::template load<CP>(rb, vcol, so);
+        rupv[q] = IO::template load<CP>(rup, vcol, so);
     };
 #pragma unroll
     for (int q = 0; q < PF; ++q)
@@ -271,12 +281,12 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     double xn = half ? x_hi : x_lo;
     if constexpr (!VDIFF) {
         if (active && nsteps > 0)
-            IO::store_d(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, xn);
+            IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, xn);
 #pragma unroll
         for (int tt = KH - 2; tt >= 0; --tt) {
             if (tt < nsteps - 1) {
                 xn = D[tt] - P[tt] * xn;
-                if (active) IO::store_d(rx, vcol, static_cast<uint32_t>(level(tt)) * sk_bytes, xn);
+                if (active) IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(tt)) * sk_bytes, xn);
             }
         }
     } else {
@@ -293,7 +303,7 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
             const double g_up = has_up ? up - x_cur : 0.0;
             const double g_dn = has_dn ? x_cur - dn : 0.0;
             const double y = x_cur + kappa * (g_up - g_dn);
-            if (active) IO::store_d(rx, vcol, static_cast<uint32_t>(level(t_loc)) * sk_bytes, y);
+            if (active) IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(t_loc)) * sk_bytes, y);
         };
 #pragma unroll
         for (int tt = KH - 2; tt >= 0; --tt) {
@@ -308,11 +318,11 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     }
 }
 
-template <class T, bool FUSED, int TJ, int PF, int KH, int WPE>
+template <class T, bool FUSED, int TJ, int PF, int KH, int WPE, bool NT = false>
 __global__ __launch_bounds__(128 * TJ) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void
 k_column(ColumnArgs p) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
-    column_tile<T, FUSED, false, TJ, PF, KH>(p, t % p.nbi, t / p.nbi, 0.0);
+    column_tile<T, FUSED, false, TJ, PF, KH, NT>(p, t % p.nbi, t / p.nbi, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -358,12 +368,12 @@ k_column_batch(ColumnBatch b) {
 // ---------------------------------------------------------------------------
 // Host launchers, instantiated per storage type in column_<dtype>.hip.
 // ---------------------------------------------------------------------------
-template <class T, bool FUSED, int TJ, int PF, int KH, int WPE>
+template <class T, bool FUSED, int TJ, int PF, int KH, int WPE, bool NT = false>
 static hipError_t launch_column_t(ColumnArgs a, hipStream_t st) {
     a.nbi = (a.I + 63) / 64;
     a.nbj = (a.J + TJ - 1) / TJ;
-    hipLaunchKernelGGL((k_column<T, FUSED, TJ, PF, KH, WPE>), dim3(a.nbi * a.nbj), dim3(128 * TJ), 0,
-                       st, a);
+    hipLaunchKernelGGL((k_column<T, FUSED, TJ, PF, KH, WPE, NT>), dim3(a.nbi * a.nbj), dim3(128 * TJ),
+                       0, st, a);
     return hipGetLastError();
 }
 

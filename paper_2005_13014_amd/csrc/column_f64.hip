@@ -5,26 +5,26 @@
 namespace stl {
 
 // Register-resident half columns of KH levels serve nk <= 2 KH.
-template <bool FUSED, int TJ, int PF>
+template <bool FUSED, int TJ, int PF, bool NT = false>
 static hipError_t by_levels(const ColumnArgs &a, hipStream_t st) {
     const int m = (a.K + 1) / 2;
-    if (m <= 16) return launch_column_t<double, FUSED, TJ, PF, 16, 2>(a, st);
-    if (m <= 32) return launch_column_t<double, FUSED, TJ, PF, 32, 1>(a, st);
-    if (m <= 40) return launch_column_t<double, FUSED, TJ, PF, 40, 1>(a, st);
-    return launch_column_t<double, FUSED, TJ, PF, 48, 1>(a, st);
+    if (m <= 16) return launch_column_t<double, FUSED, TJ, PF, 16, 2, NT>(a, st);
+    if (m <= 32) return launch_column_t<double, FUSED, TJ, PF, 32, 1, NT>(a, st);
+    if (m <= 40) return launch_column_t<double, FUSED, TJ, PF, 40, 1, NT>(a, st);
+    return launch_column_t<double, FUSED, TJ, PF, 48, 1, NT>(a, st);
 }
 
-bool column_variant_f64(int tile_j, int prefetch) {
-    if (tile_j == 2 && prefetch == 2) return true;
-    if (tile_j == 2 && prefetch == 4) return true;
+bool column_variant_f64(int tile_j, int prefetch, bool nt) {
+    if (!nt && tile_j == 2 && prefetch == 2) return true;
+    if (!nt && tile_j == 2 && prefetch == 4) return true;
     return false;
 }
 
-hipError_t launch_column_f64(bool fused, const ColumnArgs &a, int tile_j, int prefetch,
+hipError_t launch_column_f64(bool fused, const ColumnArgs &a, int tile_j, int prefetch, bool nt,
                              hipStream_t st) {
     if (!fused) return by_levels<false, 2, 2>(a, st);
-    if (tile_j == 2 && prefetch == 2) return by_levels<true, 2, 2>(a, st);
-    if (tile_j == 2 && prefetch == 4) return by_levels<true, 2, 4>(a, st);
+    if (!nt && tile_j == 2 && prefetch == 2) return by_levels<true, 2, 2>(a, st);
+    if (!nt && tile_j == 2 && prefetch == 4) return by_levels<true, 2, 4>(a, st);
     return hipErrorInvalidValue;
 }
 

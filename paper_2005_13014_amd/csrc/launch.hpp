@@ -13,12 +13,15 @@ enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
 // Column kernels (column.hpp): register-resident half columns serve
 // nk <= KMAX_COLUMN; (tile_j, prefetch) selects a compiled fused variant.
 constexpr int KMAX_COLUMN = 96;
-bool column_variant_f64(int tile_j, int prefetch);
-bool column_variant_f32(int tile_j, int prefetch);
-bool column_variant_bf16(int tile_j, int prefetch);
-hipError_t launch_column_f64(bool fused, const ColumnArgs &a, int tile_j, int prefetch, hipStream_t st);
-hipError_t launch_column_f32(bool fused, const ColumnArgs &a, int tile_j, int prefetch, hipStream_t st);
-hipError_t launch_column_bf16(bool fused, const ColumnArgs &a, int tile_j, int prefetch, hipStream_t st);
+bool column_variant_f64(int tile_j, int prefetch, bool nt);
+bool column_variant_f32(int tile_j, int prefetch, bool nt);
+bool column_variant_bf16(int tile_j, int prefetch, bool nt);
+hipError_t launch_column_f64(bool fused, const ColumnArgs &a, int tile_j, int prefetch, bool nt,
+                              hipStream_t st);
+hipError_t launch_column_f32(bool fused, const ColumnArgs &a, int tile_j, int prefetch, bool nt,
+                              hipStream_t st);
+hipError_t launch_column_bf16(bool fused, const ColumnArgs &a, int tile_j, int prefetch, bool nt,
+                              hipStream_t st);
 
 // Horizontal diffusion alone, inlined, with j-unroll 1, 2 or 4 (hdiff.hip).
 hipError_t launch_hdiff(int dtype, const HdiffArgs &a, int unroll, hipStream_t st);

@@ -141,12 +141,12 @@ def test_config3_full_size(dtype, n):
     assert halo_untouched(x)
 
 
-@pytest.mark.parametrize("tj,pf", [(2, 4), (4, 4), (2, 2), (2, 8), (1, 4)])
-def test_fused_variants_are_bitwise_identical(tj, pf):
+@pytest.mark.parametrize("tj,pf,nt", [(2, 4, 0), (4, 4, 0), (2, 2, 0), (2, 8, 0), (1, 4, 0), (2, 4, 1)])
+def test_fused_variants_are_bitwise_identical(tj, pf, nt):
     ni, nj, nk = 200, 37, 80
     f = inputs.fields(ni, nj, nk, 2, seed=SEED + 4, storage="f32")
     base = run_hdiff_vadv(f, ni, nj, nk, 2, "f32").to_numpy(interior=True)
-    got = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(tile_j=tj, prefetch=pf))
+    got = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(tile_j=tj, prefetch=pf, nontemporal=nt))
     assert np.array_equal(got.to_numpy(interior=True), base)
 
 

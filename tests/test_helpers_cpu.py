@@ -1,0 +1,42 @@
+"""Host-side checks of the test helpers and the benchmark's command line."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import oracle
+from helpers import limiter_masks, normwise, rms_rel
+from paper_2005_13014_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_limiter_masks_in_fp64_equal_the_oracle_decisions():
+    f = inputs.fields(37, 21, 4, 2, seed=3, vadv=False)
+    _, _, _, kx, ky = oracle.hdiff(f["u"], 2, f["coeff"], 2, fluxes=True)
+    mx, my = limiter_masks(f["u"], 2, "f64")
+    assert np.array_equal(kx, mx) and np.array_equal(ky, my)
+
+
+def test_limiter_masks_fp32_are_float32_decisions():
+    # Values exactly representable in float32, so the inputs agree; the
+    # decisions may differ from FP64 only where a product sits at rounding level.
+    f = inputs.fields(64, 48, 6, 2, seed=4, vadv=False, storage="f32")
+    mx, my = limiter_masks(f["u"], 2, "f32")
+    _, _, _, kx, ky = oracle.hdiff(f["u"], 2, f["coeff"], 2, fluxes=True)
+    flips = int((mx != kx).sum() + (my != ky).sum())
+    assert flips <= 3
+
+
+def test_error_measures():
+    ref = np.array([1.0, -2.0, 4.0])
+    assert abs(normwise(ref + np.array([0, 0, 4e-6]), ref) - 1e-6) < 1e-15
+    assert rms_rel(ref, ref) == 0.0
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
