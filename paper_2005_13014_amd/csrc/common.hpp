@@ -102,10 +102,12 @@ __device__ __forceinline__ C hdiff_point(const C *t, C cf) {
 // pointer is the field's interior origin.
 // ---------------------------------------------------------------------------
 struct HdiffArgs {
-    const void *u, *coeff;
+    const void *u, *coeff;  // interior origins
     void *out;
     int I, J, K, sj, sk;
-    int nbi, nbj;  // tiles in i and j
+    int nbi, nbj;           // tiles in i and j
+    uint32_t u_bytes;       // addressable bytes from u's cell (-2, -2, 0)
+    uint32_t col_bytes;     // addressable bytes from an interior origin
 };
 
 // Column kernels (fused hdiff + vadv, vadv alone); see column.hpp.

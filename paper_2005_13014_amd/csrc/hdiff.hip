@@ -11,6 +11,7 @@
 // The inputs of the next PF levels are prefetched into registers.
 #include <type_traits>
 
+#include "column.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -27,60 +28,73 @@ __device__ __forceinline__ C limit(C f, C du) {
 }
 
 // TO = T writes the storage dtype; TO = C keeps the compute type (scratch).
+// Fields are addressed through raw buffers (column.hpp): u from its cell
+// (-2, -2, 0), coeff and out from their origins; the level offset is scalar.
 template <class T, class TO, int TJ, int UJ, int PF>
 __global__ __launch_bounds__(64 * TJ) void k_hdiff(HdiffArgs p) {
     using S = Storage<T>;
     using C = typename S::C;
+    using IO = BufIO<T>;
     constexpr int TI = 64, RJ = TJ * UJ, PI = TI + 4, PJ = RJ + 4;
     constexpr int MR = (PJ + TJ - 1) / TJ;
-    __shared__ C tile[2][PJ * PI];
+    constexpr uint32_t ES = sizeof(T);
+    __shared__ C tile[2][PJ * PI + 64];
 
-    const T *__restrict__ u = static_cast<const T *>(p.u);
-    const T *__restrict__ coeff = static_cast<const T *>(p.coeff);
-    TO *__restrict__ out = static_cast<TO *>(p.out);
-
-    const int tid = threadIdx.x, ti = tid & 63, tj = tid >> 6;
+    const int tid = threadIdx.x, ti = tid & 63;
+    const int tj = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int bi = t % p.nbi, bj = t / p.nbi;
     const int i0 = bi * TI, j0 = bj * RJ;
     const int gi = i0 + ti;
     const int jr = tj * UJ;  // first tile row (interior numbering) of this lane
+    const int I = p.I, J = p.J, sj = p.sj;
+    const uint32_t skb = static_cast<uint32_t>(p.sk) * ES;
 
-    int moff[MR], mlds[MR];
-    bool mrow[MR], mok[MR];
+    const auto ru = make_rsrc(static_cast<const char *>(p.u) - (2 + 2 * sj) * static_cast<int>(ES),
+                              p.u_bytes);
+    const auto rcf = make_rsrc(p.coeff, p.col_bytes);
+
+    // Tile element (r, c) holds u(i0 - 2 + c, j0 - 2 + r); loads past the
+    // addressable ring are clamped onto valid cells (never read by an active lane).
+    uint32_t vmain[MR];
+    int lmain[MR];
+    bool mrow[MR];
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
-        const int r = tj + m * TJ, gy = j0 - 2 + r;
+        const int r = tj + m * TJ;
         mrow[m] = r < PJ;
-        mok[m] = mrow[m] && gi < p.I + 2 && gy < p.J + 2;
-        moff[m] = gi + gy * p.sj;
-        mlds[m] = r * PI + ti + 2;
+        const int gx = min(gi, I + 1), gy = min(j0 - 2 + r, J + 1);
+        vmain[m] = static_cast<uint32_t>(gx + 2 + (gy + 2) * sj) * ES;
+        lmain[m] = r * PI + ti + 2;
     }
-    const int sr = tid >> 2, sq = tid & 3;
+    // The 4 PJ side cells are staged by lanes 0 .. 4 PJ - 1 of the workgroup,
+    // i.e. by its first (4 PJ + 63) / 64 waves; their remaining lanes write a
+    // dummy slot.
+    const bool side_wave = tj < (4 * PJ + 63) / 64;
+    const int sr = min(tid >> 2, PJ - 1), sq = tid & 3;
     const int sc = sq < 2 ? sq : sq + 64;
-    const int sgx = i0 - 2 + sc, sgy = j0 - 2 + sr;
-    const bool srow = tid < 4 * PJ;
-    const bool sok = srow && sgx < p.I + 2 && sgy < p.J + 2;
-    const int soff = sgx + sgy * p.sj;
-    const int slds = sr * PI + sc;
+    const uint32_t vside =
+        static_cast<uint32_t>(min(i0 - 2 + sc, I + 1) + 2 + (min(j0 - 2 + sr, J + 1) + 2) * sj) * ES;
+    const int lside = tid < 4 * PJ ? sr * PI + sc : PJ * PI + ti;
 
-    int coff[UJ];
+    uint32_t vcol[UJ];
     bool cact[UJ];
 #pragma unroll
     for (int v = 0; v < UJ; ++v) {
         const int gj = j0 + jr + v;
-        cact[v] = gi < p.I && gj < p.J;
-        coff[v] = min(gi, p.I - 1) + min(gj, p.J - 1) * p.sj;
+        cact[v] = gi < I && gj < J;
+        vcol[v] = static_cast<uint32_t>(min(gi, I - 1) + min(gj, J - 1) * sj) * ES;
     }
 
-    C rum[PF][MR], rus[PF], rcf[PF][UJ];
+    C rum[PF][MR], rus[PF], rcf_[PF][UJ];
     auto load = [&](int q, int k) {
-        const int ko = k * p.sk;
+        const uint32_t so = static_cast<uint32_t>(k) * skb;
 #pragma unroll
-        for (int m = 0; m < MR; ++m) rum[q][m] = mok[m] ? S::load(u + moff[m] + ko) : C(0);
-        rus[q] = sok ? S::load(u + soff + ko) : C(0);
+        for (int m = 0; m < MR; ++m)
+            if (mrow[m]) rum[q][m] = IO::load(ru, vmain[m], so);
+        if (side_wave) rus[q] = IO::load(ru, vside, so);
 #pragma unroll
-        for (int v = 0; v < UJ; ++v) rcf[q][v] = S::load(coeff + coff[v] + ko);
+        for (int v = 0; v < UJ; ++v) rcf_[q][v] = IO::load(rcf, vcol[v], so);
     };
 
     const int K = p.K;
@@ -96,11 +110,11 @@ __global__ __launch_bounds__(64 * TJ) void k_hdiff(HdiffArgs p) {
                 C *tb = tile[q & 1];  // PF is even, so q & 1 == k & 1
 #pragma unroll
                 for (int m = 0; m < MR; ++m)
-                    if (mrow[m]) tb[mlds[m]] = rum[q][m];
-                if (srow) tb[slds] = rus[q];
+                    if (mrow[m]) tb[lmain[m]] = rum[q][m];
+                if (side_wave) tb[lside] = rus[q];
                 C cf[UJ];
 #pragma unroll
-                for (int v = 0; v < UJ; ++v) cf[v] = rcf[q][v];
+                for (int v = 0; v < UJ; ++v) cf[v] = rcf_[q][v];
                 if (k + PF < K) load(q, k + PF);
                 __syncthreads();
 
@@ -124,10 +138,11 @@ __global__ __launch_bounds__(64 * TJ) void k_hdiff(HdiffArgs p) {
                     const C fw = limit(lc[v + 1] - lw, uc[v + 1] - cv[-1]);
                     const C h = uc[v + 1] - cf[v] * (fe - fw + fy[v + 1] - fy[v]);
                     if (cact[v]) {
+                        const uint32_t o = vcol[v] / ES + static_cast<uint32_t>(k) * p.sk;
                         if constexpr (std::is_same<TO, C>::value)
-                            out[coff[v] + k * p.sk] = h;
+                            static_cast<TO *>(p.out)[o] = h;
                         else
-                            S::store(out + coff[v] + k * p.sk, h);
+                            S::store(static_cast<TO *>(p.out) + o, h);
                     }
                 }
             }
@@ -139,6 +154,11 @@ template <class T, int TJ, int UJ, int PF, class TO = T>
 static hipError_t launch_hdiff_t(HdiffArgs a, hipStream_t st) {
     a.nbi = (a.I + 63) / 64;
     a.nbj = (a.J + TJ * UJ - 1) / (TJ * UJ);
+    const long long es = sizeof(T);
+    a.u_bytes = static_cast<uint32_t>(((a.I + 3) + static_cast<long long>(a.J + 3) * a.sj +
+                                       static_cast<long long>(a.K - 1) * a.sk + 1) * es);
+    a.col_bytes = static_cast<uint32_t>(((a.I - 1) + static_cast<long long>(a.J - 1) * a.sj +
+                                         static_cast<long long>(a.K - 1) * a.sk + 1) * es);
     hipLaunchKernelGGL((k_hdiff<T, TO, TJ, UJ, PF>), dim3(a.nbi * a.nbj), dim3(64 * TJ), 0, st, a);
     return hipGetLastError();
 }
