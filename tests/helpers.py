@@ -42,10 +42,13 @@ def out_field(ni, nj, nk, halo, dtype, canary=-7.0):
 
 
 def halo_untouched(field, canary=-7.0):
-    p = field.to_numpy()
-    mask = np.ones(p.shape, bool)
-    mask[:, field.hj:field.hj + field.nj, field.hi:field.hi + field.ni] = False
-    return bool(np.all(p[mask] == canary))
+    """Every element of the field's allocation outside its interior (halo,
+    row and plane padding, alignment slack) still holds the canary."""
+    buf = field.buf.detach().to("cpu").double().numpy()
+    mask = np.ones(buf.shape, bool)
+    k, j, i = np.meshgrid(np.arange(field.nk), np.arange(field.nj), np.arange(field.ni), indexing="ij")
+    mask[field.origin + i + field.sj * j + field.sk * k] = False
+    return bool(np.all(buf[mask] == canary))
 
 
 def limiter_masks(u_padded, h, storage):
