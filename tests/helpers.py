@@ -15,14 +15,20 @@ TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2.0 ** -8 + 1e-5}
 
 
 def normwise(x, ref):
-    den = np.abs(ref).max() if ref.size else 1.0
-    return float(np.abs(x - ref).max() / den) if x.size else 0.0
+    """max|x - ref| / max|ref|; an all-zero reference makes it the absolute error."""
+    if not x.size:
+        return 0.0
+    den = np.abs(ref).max()
+    err = np.abs(x - ref).max()
+    return float(err / den) if den > 0 else float(err)
 
 
 def rms_rel(x, ref):
     if not x.size:
         return 0.0
-    return float(np.sqrt(np.mean((x - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))
+    den = np.sqrt(np.mean(ref ** 2))
+    err = np.sqrt(np.mean((x - ref) ** 2))
+    return float(err / den) if den > 0 else float(err)
 
 
 def interior(a, h):
