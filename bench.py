@@ -254,7 +254,7 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16"])
     ap.add_argument("--tile-j", type=int, default=0)
     ap.add_argument("--prefetch", type=int, default=0)
-    ap.add_argument("--nontemporal", type=int, default=0)
+    ap.add_argument("--nontemporal", type=int, default=0, help="1 on, -1 off, 0 library choice")
     ap.add_argument("--quick", action="store_true",
                     help="only the headline measurement (no variants, no CPU baseline)")
     ap.add_argument("--with-copy", action="store_true",

@@ -95,8 +95,9 @@ typedef struct {
     int32_t unroll;   /* j-unroll factor of stencil_hdiff: 1, 2 or 4 (Sec. V-A) */
     int32_t tile_j;   /* rows of columns per workgroup: 1, 2 or 4 (fused kernels) */
     int32_t prefetch; /* k-levels loaded ahead of use: 2, 4 or 8 */
-    int32_t nontemporal; /* 1: read-once inputs and the output bypass cache
-                            retention (non-temporal loads and stores) */
+    int32_t nontemporal; /* read-once inputs and the output use non-temporal
+                            loads and stores: 1 on, -1 off, 0 the library's
+                            choice (on wherever the variant is compiled) */
 } stencil_config_t;
 
 /* Horizontal diffusion, per level k and interior point (i, j):
@@ -130,7 +131,7 @@ int stencil_vadv(const stencil_field_t *h, const stencil_field_t *wcon,
  * inlining (Sec. V-A) of the two stages.  With level ORIGINAL it runs one
  * kernel per operator through library-owned device scratch instead.
  * Inputs: u (halo >= 2), coeff, wcon, a, b, c (interior read only).
- * Output: x.  cfg: level, tile_j, prefetch. */
+ * Output: x.  cfg: level, tile_j, prefetch, nontemporal. */
 int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field_t *coeff,
                        const stencil_field_t *wcon, const stencil_field_t *a,
                        const stencil_field_t *b, const stencil_field_t *c, double dt,

@@ -21,6 +21,9 @@ bool column_variant_f32(int tile_j, int prefetch, bool nt) {
     if (!nt && tile_j == 2 && prefetch == 8) return true;
     if (!nt && tile_j == 1 && prefetch == 4) return true;
     if (nt && tile_j == 2 && prefetch == 4) return true;
+    if (nt && tile_j == 4 && prefetch == 4) return true;
+    if (nt && tile_j == 2 && prefetch == 8) return true;
+    if (nt && tile_j == 2 && prefetch == 2) return true;
     return false;
 }
 
@@ -33,6 +36,9 @@ hipError_t launch_column_f32(bool fused, const ColumnArgs &a, int tile_j, int pr
     if (!nt && tile_j == 2 && prefetch == 8) return by_levels<true, 2, 8>(a, st);
     if (!nt && tile_j == 1 && prefetch == 4) return by_levels<true, 1, 4>(a, st);
     if (nt && tile_j == 2 && prefetch == 4) return by_levels<true, 2, 4, true>(a, st);
+    if (nt && tile_j == 4 && prefetch == 4) return by_levels<true, 4, 4, true>(a, st);
+    if (nt && tile_j == 2 && prefetch == 8) return by_levels<true, 2, 8, true>(a, st);
+    if (nt && tile_j == 2 && prefetch == 2) return by_levels<true, 2, 2, true>(a, st);
     return hipErrorInvalidValue;
 }
 

@@ -141,7 +141,8 @@ def test_config3_full_size(dtype, n):
     assert halo_untouched(x)
 
 
-@pytest.mark.parametrize("tj,pf,nt", [(2, 4, 0), (4, 4, 0), (2, 2, 0), (2, 8, 0), (1, 4, 0), (2, 4, 1)])
+@pytest.mark.parametrize("tj,pf,nt", [(2, 4, -1), (4, 4, -1), (2, 2, -1), (2, 8, -1), (1, 4, -1),
+                                      (2, 4, 1), (4, 4, 1), (2, 8, 1), (2, 2, 1)])
 def test_fused_variants_are_bitwise_identical(tj, pf, nt):
     ni, nj, nk = 200, 37, 80
     f = inputs.fields(ni, nj, nk, 2, seed=SEED + 4, storage="f32")
