@@ -255,6 +255,7 @@ def main():
     ap.add_argument("--tile-j", type=int, default=0)
     ap.add_argument("--prefetch", type=int, default=0)
     ap.add_argument("--nontemporal", type=int, default=0, help="1 on, -1 off, 0 library choice")
+    ap.add_argument("--schedule", type=int, default=0, help="1 staged, 2 pipelined, 0 library choice")
     ap.add_argument("--quick", action="store_true",
                     help="only the headline measurement (no variants, no CPU baseline)")
     ap.add_argument("--with-copy", action="store_true",
@@ -274,7 +275,8 @@ def main():
     ni, nj, nk = args.size
     dtype = args.dtype
     es = ES[dtype]
-    cfg = B.config(tile_j=args.tile_j, prefetch=args.prefetch, nontemporal=args.nontemporal)
+    cfg = B.config(tile_j=args.tile_j, prefetch=args.prefetch, nontemporal=args.nontemporal,
+                   schedule=args.schedule)
     abytes = fused_bytes(ni, nj, nk, es)
     nsets = n_sets_for(abytes)
     log("generating %d input sets %dx%dx%d %s" % (nsets, ni, nj, nk, dtype))
@@ -285,7 +287,7 @@ def main():
     achieved = abytes / (kern * 1e-3) / 1e9
     log("wall %.4f ms/step, kernel %.4f ms, %.1f GB/s algorithmic" % (wall, kern, achieved))
     headline = ((ni, nj, nk, dtype) == (512, 512, 80, "f32")
-                and not (args.tile_j or args.prefetch or args.nontemporal))
+                and not (args.tile_j or args.prefetch or args.nontemporal or args.schedule))
     traffic = measured_traffic() if headline else None
 
     result = {

@@ -98,6 +98,10 @@ typedef struct {
     int32_t nontemporal; /* read-once inputs and the output use non-temporal
                             loads and stores: 1 on, -1 off, 0 the library's
                             choice (on wherever the variant is compiled) */
+    int32_t schedule; /* level loop of the fused kernel: 1 staged (each level
+                         is staged, evaluated and eliminated in turn), 2
+                         pipelined (hdiff of level s overlaps the elimination
+                         of level s-2), 0 the library's choice */
 } stencil_config_t;
 
 /* Horizontal diffusion, per level k and interior point (i, j):
@@ -131,7 +135,7 @@ int stencil_vadv(const stencil_field_t *h, const stencil_field_t *wcon,
  * inlining (Sec. V-A) of the two stages.  With level ORIGINAL it runs one
  * kernel per operator through library-owned device scratch instead.
  * Inputs: u (halo >= 2), coeff, wcon, a, b, c (interior read only).
- * Output: x.  cfg: level, tile_j, prefetch, nontemporal. */
+ * Output: x.  cfg: level, tile_j, prefetch, nontemporal, schedule. */
 int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field_t *coeff,
                        const stencil_field_t *wcon, const stencil_field_t *a,
                        const stencil_field_t *b, const stencil_field_t *c, double dt,

@@ -212,21 +212,53 @@ static int run_plain(int dtype, PlainArgs a, hipStream_t st) {
     return launch_status(launch_plain(dtype, a, st), "unfused kernels");
 }
 
-static hipError_t launch_column(int dtype, bool fused, const ColumnArgs &a, int tj, int pf, bool nt,
+static hipError_t launch_column(int dtype, bool fused, const ColumnArgs &a, const ColumnVariant &v,
                                 hipStream_t st) {
     switch (dtype) {
-    case STENCIL_F64: return launch_column_f64(fused, a, tj, pf, nt, st);
-    case STENCIL_F32: return launch_column_f32(fused, a, tj, pf, nt, st);
-    default: return launch_column_bf16(fused, a, tj, pf, nt, st);
+    case STENCIL_F64: return launch_column_f64(fused, a, v, st);
+    case STENCIL_F32: return launch_column_f32(fused, a, v, st);
+    default: return launch_column_bf16(fused, a, v, st);
     }
 }
 
-static bool column_variant(int dtype, int tj, int pf, bool nt) {
+static bool column_variant(int dtype, const ColumnVariant &v) {
     switch (dtype) {
-    case STENCIL_F64: return column_variant_f64(tj, pf, nt);
-    case STENCIL_F32: return column_variant_f32(tj, pf, nt);
-    default: return column_variant_bf16(tj, pf, nt);
+    case STENCIL_F64: return column_variant_f64(v);
+    case STENCIL_F32: return column_variant_f32(v);
+    default: return column_variant_bf16(v);
     }
+}
+
+// Resolves the fused variant from the knobs; zero knobs take the fastest
+// variant measured at 512 x 512 x 80 (FP32: two rows of 64 columns per half,
+// eight levels prefetched, non-temporal streams).  A non-zero knob that names
+// no compiled variant is an error, not a silent substitution.
+static int fused_variant(int dtype, const stencil_config_t &cf, ColumnVariant *out) {
+    ColumnVariant v{};
+    v.tile_j = cf.tile_j ? cf.tile_j : 2;
+    v.prefetch = cf.prefetch ? cf.prefetch : dtype == STENCIL_F64 ? 2 : dtype == STENCIL_F32 ? 8 : 4;
+    if (cf.nontemporal < -1 || cf.nontemporal > 1)
+        return fail(STENCIL_E_ARG, "nontemporal must be -1, 0 or 1 (got %d)", cf.nontemporal);
+    if (cf.schedule < 0 || cf.schedule > 2)
+        return fail(STENCIL_E_ARG, "schedule must be 0, 1 or 2 (got %d)", cf.schedule);
+    const bool nts[2] = {true, false};
+    const bool pipes[2] = {false, true};
+    bool found = false;
+    for (int q = 0; q < 2 && !found; ++q) {
+        v.nt = nts[q];
+        if ((cf.nontemporal > 0 && !v.nt) || (cf.nontemporal < 0 && v.nt)) continue;
+        for (int r = 0; r < 2 && !found; ++r) {
+            v.pipe = pipes[r];
+            if ((cf.schedule == 1 && v.pipe) || (cf.schedule == 2 && !v.pipe)) continue;
+            found = column_variant(dtype, v);
+        }
+    }
+    if (cf.level != STENCIL_LEVEL_ORIGINAL && !found)
+        return fail(STENCIL_E_UNSUPPORTED,
+                    "no compiled fused variant tile_j=%d prefetch=%d nontemporal=%d schedule=%d", v.tile_j,
+                    v.prefetch, cf.nontemporal, cf.schedule);
+    *out = v;
+    return STENCIL_OK;
 }
 
 // Column kernels address every field through a raw buffer of < 2^31 bytes.
@@ -336,7 +368,7 @@ STENCIL_API int stencil_vadv(const stencil_field_t *h, const stencil_field_t *wc
         return run_plain(dtype, p, st);
     }
     const ColumnArgs v = column_args(h, nullptr, wcon, a, b, c, x, dt, false);
-    return launch_status(launch_column(dtype, false, v, 0, 0, false, st), "vadv kernel");
+    return launch_status(launch_column(dtype, false, v, ColumnVariant{}, st), "vadv kernel");
 }
 
 STENCIL_API int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field_t *coeff,
@@ -353,14 +385,8 @@ STENCIL_API int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field
     if (cf.level < 0 || cf.level > STENCIL_LEVEL_INLINE)
         return fail(STENCIL_E_ARG, "unknown level %d", cf.level);
     const int dtype = u->dtype;
-    // Defaults: the fastest variant measured at 512 x 512 x 80 (FP32: two rows of
-    // 64 columns per half, eight levels prefetched, non-temporal streams).
-    const int tj = cf.tile_j ? cf.tile_j : 2;
-    const int pf = cf.prefetch ? cf.prefetch : dtype == STENCIL_F64 ? 2 : dtype == STENCIL_F32 ? 8 : 4;
-    const bool nt = cf.nontemporal > 0 || (cf.nontemporal == 0 && column_variant(dtype, tj, pf, true));
-    if (cf.level != STENCIL_LEVEL_ORIGINAL && !column_variant(dtype, tj, pf, nt))
-        return fail(STENCIL_E_UNSUPPORTED, "no compiled fused variant tile_j=%d prefetch=%d nontemporal=%d",
-                    tj, pf, cf.nontemporal);
+    ColumnVariant var{};
+    TRY(fused_variant(dtype, cf, &var));
     if (empty(u)) return STENCIL_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (cf.level == STENCIL_LEVEL_ORIGINAL || u->nk > KMAX_COLUMN || !column_fits(u)) {
@@ -378,7 +404,7 @@ STENCIL_API int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field
         return run_plain(dtype, p, st);
     }
     const ColumnArgs v = column_args(u, coeff, wcon, a, b, c, x, dt, true);
-    return launch_status(launch_column(dtype, true, v, tj, pf, nt, st), "fused hdiff+vadv kernel");
+    return launch_status(launch_column(dtype, true, v, var, st), "fused hdiff+vadv kernel");
 }
 
 STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stencil_field_t *coeff,

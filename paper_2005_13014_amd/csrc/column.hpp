@@ -97,6 +97,11 @@ __device__ __forceinline__ double recip(double m) {
     return __builtin_fma(r, e, r);
 }
 
+// Marks a value as produced here: the compiler may not defer its arithmetic
+// past this point (left alone, it sinks a straight-line level loop's whole
+// elimination below the last barrier and spills the loaded operands).
+__device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
+
 
 // ---------------------------------------------------------------------------
 // Workgroup = 2 halves x (64 x TJ lanes); the tile is 64 x TJ columns.
@@ -106,8 +111,12 @@ __device__ __forceinline__ double recip(double m) {
 // level by level during the back-substitution.
 // NT: the read-once column inputs and the output use non-temporal accesses
 // (u is re-read by neighbouring tiles through L2 and keeps the default).
-template <class T, bool FUSED, bool VDIFF, int TJ, int PF, int KH, bool NT = false>
+// EXACT: nk == 2 KH, so both halves take exactly KH levels; every level
+// guard is then a compile-time constant and each barrier interval of the
+// level loop is one straight-line scheduling region.
+template <class T, bool FUSED, bool VDIFF, int TJ, int PF, int KH, bool NT = false, bool EXACT = false>
 __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj, double kappa) {
+#pragma clang fp contract(off)
     using S = Storage<T>;
     using C = typename S::C;
     using IO = BufIO<T>;
@@ -166,9 +175,9 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
         static_cast<uint32_t>(min(i0 - 2 + sc, I + 1) + 2 + (min(j0 - 2 + sr, J + 1) + 2) * sj) * ES;
     const int lside = l < 4 * PJ ? sr * PI + sc : PJ * PI + ti;
 
-    const int M = (K + 1) >> 1;
-    const int nsteps = half ? K - M : M;
-    auto level = [&](int s) { return half ? K - 1 - s : s; };
+    const int M = EXACT ? KH : (K + 1) >> 1;
+    const int nsteps = EXACT ? KH : half ? K - M : M;
+    auto level = [&](int s) { return half ? (EXACT ? 2 * KH : K) - 1 - s : s; };
 
     C rum[PF][FUSED ? MR : 1], rus[PF], rcfv[PF], rwv[PF], rlov[PF], rbv[PF], rupv[PF];
     auto load = [&](int q, int s) {
@@ -225,7 +234,7 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
                     // Face between the previous and this level; right-hand side
                     // and elimination of the previous level.
                     const C f_new = (C(0.5) * (w_prev + wv)) * (C(0.5) * (h_prev + h));
-                    const double d = static_cast<double>(h_prev - dts * (f_new - f_old));
+                    const double d = static_cast<double>(fmadd(-dts, f_new - f_old, h_prev));
                     const int tt = s > 0 ? s - 1 : 0;
                     if (tt == 0) {
                         const double r = recip(b_prev);
@@ -233,9 +242,13 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
                         D[0] = d * r;
                     } else {
                         const int tm = tt > 0 ? tt - 1 : 0;
-                        const double r = recip(b_prev - lo_prev * P[tm]);
+                        const double r = recip(fmadd(-lo_prev, P[tm], b_prev));
                         P[tt] = up_prev * r;
-                        D[tt] = (d - lo_prev * D[tm]) * r;
+                        D[tt] = fmadd(-lo_prev, D[tm], d) * r;
+                    }
+                    if constexpr (EXACT) {
+                        pin(P[tt]);
+                        pin(D[tt]);
                     }
                     P_last = P[tt];
                     D_last = D[tt];
@@ -259,11 +272,11 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
         f_mid = (C(0.5) * (w_prev + static_cast<C>(o1.y))) * (C(0.5) * (h_prev + static_cast<C>(o1.x)));
     double Pm = 0.0, Dm = 0.0;  // this half's eliminated interface row
     if (nsteps > 0) {
-        const double d = static_cast<double>(h_prev - dts * (f_mid - f_old));
-        const double m = nsteps > 1 ? b_prev - lo_prev * P_last : b_prev;
+        const double d = static_cast<double>(fmadd(-dts, f_mid - f_old, h_prev));
+        const double m = nsteps > 1 ? fmadd(-lo_prev, P_last, b_prev) : b_prev;
         const double r = recip(m);
         Pm = up_prev * r;
-        Dm = (nsteps > 1 ? d - lo_prev * D_last : d) * r;
+        Dm = (nsteps > 1 ? fmadd(-lo_prev, D_last, d) : d) * r;
     }
     __syncthreads();
     // Interface, part 2: x(M-1) + P0 x(M) = D0 and x(M) + P1 x(M-1) = D1.
@@ -272,8 +285,8 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     const double2 o2 = xch[half ? l : NH + l];
     const double P0 = half ? o2.x : Pm, D0 = half ? o2.y : Dm;
     const double P1 = half ? Pm : o2.x, D1 = half ? Dm : o2.y;
-    const double x_lo = (D0 - P0 * D1) / (1.0 - P0 * P1);  // x(M-1)
-    const double x_hi = D1 - P1 * x_lo;                     // x(M)
+    const double x_lo = fmadd(-P0, D1, D0) / fmadd(-P0, P1, 1.0);  // x(M-1)
+    const double x_hi = fmadd(-P1, x_lo, D1);                     // x(M)
 
     // Back-substitution outward from the interface.  Local index t counts
     // from the far end of this half's levels (level(t)); the walk runs from
@@ -285,7 +298,7 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
 #pragma unroll
         for (int tt = KH - 2; tt >= 0; --tt) {
             if (tt < nsteps - 1) {
-                xn = D[tt] - P[tt] * xn;
+                xn = fmadd(-P[tt], xn, D[tt]);
                 if (active) IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(tt)) * sk_bytes, xn);
             }
         }
@@ -302,13 +315,13 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
             const bool has_up = half ? has_away : has_toward, has_dn = half ? has_toward : has_away;
             const double g_up = has_up ? up - x_cur : 0.0;
             const double g_dn = has_dn ? x_cur - dn : 0.0;
-            const double y = x_cur + kappa * (g_up - g_dn);
+            const double y = fmadd(kappa, g_up - g_dn, x_cur);
             if (active) IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(t_loc)) * sk_bytes, y);
         };
 #pragma unroll
         for (int tt = KH - 2; tt >= 0; --tt) {
             if (tt < nsteps - 1) {
-                const double xt = D[tt] - P[tt] * x_cur;
+                const double xt = fmadd(-P[tt], x_cur, D[tt]);
                 finish(tt + 1, x_in, tt + 1 < nsteps - 1 || has_other, xt, true);
                 x_in = x_cur;
                 x_cur = xt;
@@ -318,11 +331,228 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     }
 }
 
-template <class T, bool FUSED, int TJ, int PF, int KH, int WPE, bool NT = false>
+// Software-pipelined form of the fused tile (same arithmetic, same results).
+// Step s of a half: stage the tile of level s+1 into a triple-buffered LDS
+// ring and refill the register ring; evaluate hdiff at level s from the tile
+// staged one step earlier; form d(s-1); eliminate level s-2, whose inputs were
+// ready a step ago, so its double-precision chain is independent of this
+// step's hdiff and the two interleave; one barrier closes the step.
+template <class T, int TJ, int PF, int KH, bool NT, bool EXACT>
+__device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int bi, int bj) {
+#pragma clang fp contract(off)
+    using S = Storage<T>;
+    using C = typename S::C;
+    using IO = BufIO<T>;
+    constexpr int CP = NT ? 2 : 0;
+    constexpr int TI = 64, PI = TI + 4, PJ = TJ + 4, MR = PJ / TJ, NH = 64 * TJ;
+    static_assert(PJ % TJ == 0, "tile rows must split evenly over the lanes");
+    constexpr int TILE = PJ * PI + 64;
+    constexpr uint32_t ES = sizeof(T);
+    __shared__ C tile[2 * 3 * TILE];
+    __shared__ double2 xch[2 * NH];
+
+    const int tid = threadIdx.x;
+    const int half = __builtin_amdgcn_readfirstlane(tid >= NH ? 1 : 0);
+    const int l = tid - half * NH, ti = l & 63;
+    const int tj = __builtin_amdgcn_readfirstlane(l >> 6);
+    const int i0 = bi * TI, j0 = bj * TJ;
+    const int gi = i0 + ti, gj = j0 + tj;
+    const bool active = gi < p.I && gj < p.J;
+    const int I = p.I, J = p.J, K = p.K, sj = p.sj;
+    const uint32_t vcol = static_cast<uint32_t>(min(gi, I - 1) + min(gj, J - 1) * sj) * ES;
+    const uint32_t sk_bytes = static_cast<uint32_t>(p.sk) * ES;
+
+    const auto ru = make_rsrc(p.u, p.u_bytes);
+    const auto rcf = make_rsrc(p.coeff, p.col_bytes);
+    const auto rw = make_rsrc(p.wcon, p.col_bytes);
+    const auto rlo = make_rsrc(half ? p.c : p.a, p.col_bytes);
+    const auto rb = make_rsrc(p.b, p.col_bytes);
+    const auto rup = make_rsrc(half ? p.a : p.c, p.col_bytes);
+    const auto rx = make_rsrc(p.x, p.col_bytes);
+
+    uint32_t vmain[MR];
+    int lmain[MR];
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+        const int r = tj + m * TJ;
+        const int gx = min(gi, I + 1), gy = min(j0 - 2 + r, J + 1);
+        vmain[m] = static_cast<uint32_t>(gx + 2 + (gy + 2) * sj) * ES;
+        lmain[m] = r * PI + ti + 2;
+    }
+    const bool side_wave = tj == 0;
+    const int sr = min(l >> 2, PJ - 1), sq = l & 3;
+    const int sc = sq < 2 ? sq : sq + 64;
+    const uint32_t vside =
+        static_cast<uint32_t>(min(i0 - 2 + sc, I + 1) + 2 + (min(j0 - 2 + sr, J + 1) + 2) * sj) * ES;
+    const int lside = l < 4 * PJ ? sr * PI + sc : PJ * PI + ti;
+
+    const int M = EXACT ? KH : (K + 1) >> 1;
+    const int nsteps = EXACT ? KH : half ? K - M : M;
+    auto level = [&](int s) { return half ? (EXACT ? 2 * KH : K) - 1 - s : s; };
+
+    C rum[PF][MR], rus[PF], rcfv[PF], rwv[PF], rlov[PF], rbv[PF], rupv[PF];
+    auto load = [&](int q, int s) {
+        const uint32_t so = static_cast<uint32_t>(level(s)) * sk_bytes;
+#pragma unroll
+        for (int m = 0; m < MR; ++m) rum[q][m] = IO::load(ru, vmain[m], so);
+        if (side_wave) rus[q] = IO::load(ru, vside, so);
+        rcfv[q] = IO::template load<CP>(rcf, vcol, so);
+        rwv[q] = IO::template load<CP>(rw, vcol, so);
+        rlov[q] = IO::template load<CP>(rlo, vcol, so);
+        rbv[q] = IO::template load<CP>(rb, vcol, so);
+        rupv[q] = IO::template load<CP>(rup, vcol, so);
+    };
+    // Column values of the level whose hdiff comes next ("cur").
+    C cf_c = C(0), w_c = C(0);
+    double lo_c = 0.0, b_c = 1.0, up_c = 0.0;
+    auto stage = [&](int s) {  // tile and column values of level s from the ring
+        const int q = s % PF;
+        C *tb = &tile[(half * 3 + s % 3) * TILE];
+#pragma unroll
+        for (int m = 0; m < MR; ++m) tb[lmain[m]] = rum[q][m];
+        if (side_wave) tb[lside] = rus[q];
+        cf_c = rcfv[q];
+        w_c = rwv[q];
+        lo_c = static_cast<double>(rlov[q]);
+        b_c = static_cast<double>(rbv[q]);
+        up_c = static_cast<double>(rupv[q]);
+        if (s + PF < nsteps) load(q, s + PF);
+    };
+
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+        if (q < nsteps) load(q, q);
+    if (nsteps > 0) stage(0);
+    __syncthreads();
+
+    const C dts = half ? -static_cast<C>(p.dt) : static_cast<C>(p.dt);
+    C h_prev = C(0), w_prev = C(0), f_old = C(0);
+    double lo_prev = 0.0, b_prev = 1.0, up_prev = 0.0;           // level s-1
+    double d_pend = 0.0, lo_pend = 0.0, b_pend = 1.0, up_pend = 0.0;  // level s-2
+    double P[KH], D[KH];
+    double P_last = 0.0, D_last = 0.0;
+
+#pragma unroll
+    for (int s = 0; s <= KH; ++s) {
+        if (s >= 2 && s == nsteps) {
+            // Past the last step: eliminate the level before the last, the
+            // one the last step left pending.
+            const int t = s >= 2 ? s - 2 : 0;
+            if (t == 0) {
+                const double r = recip(b_pend);
+                P[0] = up_pend * r;
+                D[0] = d_pend * r;
+            } else {
+                const int tm = t > 0 ? t - 1 : 0;
+                const double r = recip(fmadd(-lo_pend, P[tm], b_pend));
+                P[t] = up_pend * r;
+                D[t] = fmadd(-lo_pend, D[tm], d_pend) * r;
+            }
+            P_last = P[t];
+            D_last = D[t];
+        }
+        if (s < M) {
+            if (s < nsteps) {
+                // Values of level s (staged one step ago) before the next stage overwrites them.
+                const C cf = cf_c, wv = w_c;
+                const double lov = lo_c, bv = b_c, upv = up_c;
+                if (s + 1 < nsteps) stage(s + 1);
+                const C *tb = &tile[(half * 3 + s % 3) * TILE];
+                const C h = hdiff_point<C, PI>(tb + (tj + 2) * PI + ti + 2, cf);
+                if (s >= 2) {
+                    const int t = s >= 2 ? s - 2 : 0;
+                    if (t == 0) {
+                        const double r = recip(b_pend);
+                        P[0] = up_pend * r;
+                        D[0] = d_pend * r;
+                    } else {
+                        const int tm = t > 0 ? t - 1 : 0;
+                        const double r = recip(fmadd(-lo_pend, P[tm], b_pend));
+                        P[t] = up_pend * r;
+                        D[t] = fmadd(-lo_pend, D[tm], d_pend) * r;
+                    }
+                    if constexpr (EXACT) {
+                        pin(P[t]);
+                        pin(D[t]);
+                    }
+                    P_last = P[t];
+                    D_last = D[t];
+                }
+                if (s >= 1) {
+                    const C f_new = (C(0.5) * (w_prev + wv)) * (C(0.5) * (h_prev + h));
+                    d_pend = static_cast<double>(fmadd(-dts, f_new - f_old, h_prev));
+                    f_old = f_new;
+                    lo_pend = lo_prev;
+                    b_pend = b_prev;
+                    up_pend = up_prev;
+                }
+                h_prev = h;
+                w_prev = wv;
+                lo_prev = lov;
+                b_prev = bv;
+                up_prev = upv;
+            }
+            __syncthreads();
+        }
+    }
+    // Interface, part 1: the face between levels M-1 and M.
+    xch[tid] = make_double2(static_cast<double>(h_prev), static_cast<double>(w_prev));
+    __syncthreads();
+    const double2 o1 = xch[half ? l : NH + l];
+    C f_mid = C(0);
+    if (K - M > 0)
+        f_mid = (C(0.5) * (w_prev + static_cast<C>(o1.y))) * (C(0.5) * (h_prev + static_cast<C>(o1.x)));
+    double Pm = 0.0, Dm = 0.0;
+    if (nsteps > 0) {
+        const double d = static_cast<double>(fmadd(-dts, f_mid - f_old, h_prev));
+        const double m = nsteps > 1 ? fmadd(-lo_prev, P_last, b_prev) : b_prev;
+        const double r = recip(m);
+        Pm = up_prev * r;
+        Dm = (nsteps > 1 ? fmadd(-lo_prev, D_last, d) : d) * r;
+    }
+    __syncthreads();
+    xch[tid] = make_double2(Pm, Dm);
+    __syncthreads();
+    const double2 o2 = xch[half ? l : NH + l];
+    const double P0 = half ? o2.x : Pm, D0 = half ? o2.y : Dm;
+    const double P1 = half ? Pm : o2.x, D1 = half ? Dm : o2.y;
+    const double x_lo = fmadd(-P0, D1, D0) / fmadd(-P0, P1, 1.0);
+    const double x_hi = fmadd(-P1, x_lo, D1);
+
+    double xn = half ? x_hi : x_lo;
+    if (active && nsteps > 0)
+        IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, xn);
+#pragma unroll
+    for (int tt = KH - 2; tt >= 0; --tt) {
+        if (tt < nsteps - 1) {
+            xn = fmadd(-P[tt], xn, D[tt]);
+            if (active) IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(tt)) * sk_bytes, xn);
+        }
+    }
+}
+
+template <class T, int TJ, int PF, int KH, int WPE, bool NT, bool EXACT>
+__global__ __launch_bounds__(128 * TJ) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void
+k_column_pipe(ColumnArgs p) {
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    column_tile_pipe<T, TJ, PF, KH, NT, EXACT>(p, t % p.nbi, t / p.nbi);
+}
+
+template <class T, int TJ, int PF, int KH, int WPE, bool NT, bool EXACT = false>
+static hipError_t launch_column_pipe_t(ColumnArgs a, hipStream_t st) {
+    if (EXACT && a.K != 2 * KH) return hipErrorInvalidValue;
+    a.nbi = (a.I + 63) / 64;
+    a.nbj = (a.J + TJ - 1) / TJ;
+    hipLaunchKernelGGL((k_column_pipe<T, TJ, PF, KH, WPE, NT, EXACT>), dim3(a.nbi * a.nbj), dim3(128 * TJ),
+                       0, st, a);
+    return hipGetLastError();
+}
+
+template <class T, bool FUSED, int TJ, int PF, int KH, int WPE, bool NT, bool EXACT>
 __global__ __launch_bounds__(128 * TJ) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void
 k_column(ColumnArgs p) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
-    column_tile<T, FUSED, false, TJ, PF, KH, NT>(p, t % p.nbi, t / p.nbi, 0.0);
+    column_tile<T, FUSED, false, TJ, PF, KH, NT, EXACT>(p, t % p.nbi, t / p.nbi, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -368,13 +598,29 @@ k_column_batch(ColumnBatch b) {
 // ---------------------------------------------------------------------------
 // Host launchers, instantiated per storage type in column_<dtype>.hip.
 // ---------------------------------------------------------------------------
-template <class T, bool FUSED, int TJ, int PF, int KH, int WPE, bool NT = false>
+template <class T, bool FUSED, int TJ, int PF, int KH, int WPE, bool NT = false, bool EXACT = false>
 static hipError_t launch_column_t(ColumnArgs a, hipStream_t st) {
+    if (EXACT && a.K != 2 * KH) return hipErrorInvalidValue;
     a.nbi = (a.I + 63) / 64;
     a.nbj = (a.J + TJ - 1) / TJ;
-    hipLaunchKernelGGL((k_column<T, FUSED, TJ, PF, KH, WPE, NT>), dim3(a.nbi * a.nbj), dim3(128 * TJ),
-                       0, st, a);
+    hipLaunchKernelGGL((k_column<T, FUSED, TJ, PF, KH, WPE, NT, EXACT>), dim3(a.nbi * a.nbj),
+                       dim3(128 * TJ), 0, st, a);
     return hipGetLastError();
+}
+
+// A compiled fused variant: its knobs and the launcher of its KH buckets.
+struct ColumnEntry {
+    int tile_j, prefetch;
+    bool nt, pipe;
+    hipError_t (*launch)(const ColumnArgs &, hipStream_t);
+};
+
+template <int N>
+static const ColumnEntry *find_column_entry(const ColumnEntry (&tab)[N], int tj, int pf, bool nt, bool pipe) {
+    for (int q = 0; q < N; ++q)
+        if (tab[q].tile_j == tj && tab[q].prefetch == pf && tab[q].nt == nt && tab[q].pipe == pipe)
+            return &tab[q];
+    return nullptr;
 }
 
 }  // namespace stl

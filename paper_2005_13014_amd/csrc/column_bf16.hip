@@ -5,8 +5,8 @@
 namespace stl {
 
 // Register-resident half columns of KH levels serve nk <= 2 KH.
-template <bool FUSED, int TJ, int PF, bool NT = false>
-static hipError_t by_levels(const ColumnArgs &a, hipStream_t st) {
+template <bool FUSED, int TJ, int PF, bool NT>
+static hipError_t staged(const ColumnArgs &a, hipStream_t st) {
     const int m = (a.K + 1) / 2;
     if (m <= 16) return launch_column_t<uint16_t, FUSED, TJ, PF, 16, 2, NT>(a, st);
     if (m <= 32) return launch_column_t<uint16_t, FUSED, TJ, PF, 32, 2, NT>(a, st);
@@ -14,18 +14,19 @@ static hipError_t by_levels(const ColumnArgs &a, hipStream_t st) {
     return launch_column_t<uint16_t, FUSED, TJ, PF, 48, 1, NT>(a, st);
 }
 
-bool column_variant_bf16(int tile_j, int prefetch, bool nt) {
-    if (!nt && tile_j == 2 && prefetch == 4) return true;
-    if (!nt && tile_j == 4 && prefetch == 4) return true;
-    return false;
+static const ColumnEntry kFused[] = {
+    {2, 4, false, false, staged<true, 2, 4, false>},
+    {4, 4, false, false, staged<true, 4, 4, false>},
+};
+
+bool column_variant_bf16(const ColumnVariant &v) {
+    return find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.pipe) != nullptr;
 }
 
-hipError_t launch_column_bf16(bool fused, const ColumnArgs &a, int tile_j, int prefetch, bool nt,
-                             hipStream_t st) {
-    if (!fused) return by_levels<false, 2, 4>(a, st);
-    if (!nt && tile_j == 2 && prefetch == 4) return by_levels<true, 2, 4>(a, st);
-    if (!nt && tile_j == 4 && prefetch == 4) return by_levels<true, 4, 4>(a, st);
-    return hipErrorInvalidValue;
+hipError_t launch_column_bf16(bool fused, const ColumnArgs &a, const ColumnVariant &v, hipStream_t st) {
+    if (!fused) return staged<false, 2, 4, false>(a, st);
+    const ColumnEntry *e = find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.pipe);
+    return e ? e->launch(a, st) : hipErrorInvalidValue;
 }
 
 }  // namespace stl

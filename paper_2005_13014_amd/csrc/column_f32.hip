@@ -5,41 +5,56 @@
 namespace stl {
 
 // Register-resident half columns of KH levels serve nk <= 2 KH.
-template <bool FUSED, int TJ, int PF, bool NT = false>
-static hipError_t by_levels(const ColumnArgs &a, hipStream_t st) {
+// Depths that fill a bucket exactly (nk = 2 KH) take a guard-free kernel.
+template <bool FUSED, int TJ, int PF, bool NT>
+static hipError_t staged(const ColumnArgs &a, hipStream_t st) {
     const int m = (a.K + 1) / 2;
-    if (m <= 16) return launch_column_t<float, FUSED, TJ, PF, 16, 2, NT>(a, st);
-    if (m <= 32) return launch_column_t<float, FUSED, TJ, PF, 32, 2, NT>(a, st);
-    if (m <= 40) return launch_column_t<float, FUSED, TJ, PF, 40, 2, NT>(a, st);
-    return launch_column_t<float, FUSED, TJ, PF, 48, 1, NT>(a, st);
+    constexpr bool X = FUSED && NT;
+    if (m <= 16) return X && a.K == 32 ? launch_column_t<float, FUSED, TJ, PF, 16, 2, NT, X>(a, st)
+                                       : launch_column_t<float, FUSED, TJ, PF, 16, 2, NT>(a, st);
+    if (m <= 32) return X && a.K == 64 ? launch_column_t<float, FUSED, TJ, PF, 32, 2, NT, X>(a, st)
+                                       : launch_column_t<float, FUSED, TJ, PF, 32, 2, NT>(a, st);
+    if (m <= 40) return X && a.K == 80 ? launch_column_t<float, FUSED, TJ, PF, 40, 2, NT, X>(a, st)
+                                       : launch_column_t<float, FUSED, TJ, PF, 40, 2, NT>(a, st);
+    return X && a.K == 96 ? launch_column_t<float, FUSED, TJ, PF, 48, 1, NT, X>(a, st)
+                          : launch_column_t<float, FUSED, TJ, PF, 48, 1, NT>(a, st);
 }
 
-bool column_variant_f32(int tile_j, int prefetch, bool nt) {
-    if (!nt && tile_j == 2 && prefetch == 4) return true;
-    if (!nt && tile_j == 4 && prefetch == 4) return true;
-    if (!nt && tile_j == 2 && prefetch == 2) return true;
-    if (!nt && tile_j == 2 && prefetch == 8) return true;
-    if (!nt && tile_j == 1 && prefetch == 4) return true;
-    if (nt && tile_j == 2 && prefetch == 4) return true;
-    if (nt && tile_j == 4 && prefetch == 4) return true;
-    if (nt && tile_j == 2 && prefetch == 8) return true;
-    if (nt && tile_j == 2 && prefetch == 2) return true;
-    return false;
+template <int TJ, int PF, bool NT>
+static hipError_t pipelined(const ColumnArgs &a, hipStream_t st) {
+    const int m = (a.K + 1) / 2;
+    if (m <= 16) return a.K == 32 ? launch_column_pipe_t<float, TJ, PF, 16, 2, NT, true>(a, st)
+                                  : launch_column_pipe_t<float, TJ, PF, 16, 2, NT>(a, st);
+    if (m <= 32) return a.K == 64 ? launch_column_pipe_t<float, TJ, PF, 32, 2, NT, true>(a, st)
+                                  : launch_column_pipe_t<float, TJ, PF, 32, 2, NT>(a, st);
+    if (m <= 40) return a.K == 80 ? launch_column_pipe_t<float, TJ, PF, 40, 2, NT, true>(a, st)
+                                  : launch_column_pipe_t<float, TJ, PF, 40, 2, NT>(a, st);
+    return a.K == 96 ? launch_column_pipe_t<float, TJ, PF, 48, 1, NT, true>(a, st)
+                     : launch_column_pipe_t<float, TJ, PF, 48, 1, NT>(a, st);
 }
 
-hipError_t launch_column_f32(bool fused, const ColumnArgs &a, int tile_j, int prefetch, bool nt,
-                             hipStream_t st) {
-    if (!fused) return by_levels<false, 2, 4>(a, st);
-    if (!nt && tile_j == 2 && prefetch == 4) return by_levels<true, 2, 4>(a, st);
-    if (!nt && tile_j == 4 && prefetch == 4) return by_levels<true, 4, 4>(a, st);
-    if (!nt && tile_j == 2 && prefetch == 2) return by_levels<true, 2, 2>(a, st);
-    if (!nt && tile_j == 2 && prefetch == 8) return by_levels<true, 2, 8>(a, st);
-    if (!nt && tile_j == 1 && prefetch == 4) return by_levels<true, 1, 4>(a, st);
-    if (nt && tile_j == 2 && prefetch == 4) return by_levels<true, 2, 4, true>(a, st);
-    if (nt && tile_j == 4 && prefetch == 4) return by_levels<true, 4, 4, true>(a, st);
-    if (nt && tile_j == 2 && prefetch == 8) return by_levels<true, 2, 8, true>(a, st);
-    if (nt && tile_j == 2 && prefetch == 2) return by_levels<true, 2, 2, true>(a, st);
-    return hipErrorInvalidValue;
+static const ColumnEntry kFused[] = {
+    {2, 4, false, false, staged<true, 2, 4, false>},
+    {4, 4, false, false, staged<true, 4, 4, false>},
+    {2, 2, false, false, staged<true, 2, 2, false>},
+    {2, 8, false, false, staged<true, 2, 8, false>},
+    {1, 4, false, false, staged<true, 1, 4, false>},
+    {2, 4, true, false, staged<true, 2, 4, true>},
+    {4, 4, true, false, staged<true, 4, 4, true>},
+    {2, 8, true, false, staged<true, 2, 8, true>},
+    {2, 2, true, false, staged<true, 2, 2, true>},
+    {2, 4, true, true, pipelined<2, 4, true>},
+    {2, 8, true, true, pipelined<2, 8, true>},
+};
+
+bool column_variant_f32(const ColumnVariant &v) {
+    return find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.pipe) != nullptr;
+}
+
+hipError_t launch_column_f32(bool fused, const ColumnArgs &a, const ColumnVariant &v, hipStream_t st) {
+    if (!fused) return staged<false, 2, 4, false>(a, st);
+    const ColumnEntry *e = find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.pipe);
+    return e ? e->launch(a, st) : hipErrorInvalidValue;
 }
 
 }  // namespace stl

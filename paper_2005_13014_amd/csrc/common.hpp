@@ -75,17 +75,26 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // limited with a select, and the update is returned.  The order of the
 // floating-point operations follows the operator definitions.
 // ---------------------------------------------------------------------------
+// Fused multiply-add in the compute type.  The fused kernels evaluate with
+// contraction off and write every fused operation out with fmadd, so that
+// the rounding sequence is fixed by the source and every schedule and tile
+// shape of a kernel gives bitwise the same result.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <class C, int PITCH>
 __device__ __forceinline__ C hdiff_point(const C *t, C cf) {
+#pragma clang fp contract(off)
     const C uc = t[0], ue = t[1], uw = t[-1], un = t[PITCH], us = t[-PITCH];
     const C uee = t[2], uww = t[-2], unn = t[2 * PITCH], uss = t[-2 * PITCH];
     const C une = t[PITCH + 1], unw = t[PITCH - 1], use = t[-PITCH + 1], usw = t[-PITCH - 1];
     const C four = C(4);
-    const C lc = four * uc - ue - uw - un - us;
-    const C le = four * ue - uee - uc - une - use;
-    const C lw = four * uw - uc - uww - unw - usw;
-    const C ln = four * un - une - unw - unn - uc;
-    const C ls = four * us - use - usw - uc - uss;
+    // 4 u is exact, so fmadd(4, u, -v) is the rounded 4 u - v.
+    const C lc = fmadd(four, uc, -ue) - uw - un - us;
+    const C le = fmadd(four, ue, -uee) - uc - une - use;
+    const C lw = fmadd(four, uw, -uc) - uww - unw - usw;
+    const C ln = fmadd(four, un, -une) - unw - unn - uc;
+    const C ls = fmadd(four, us, -use) - usw - uc - uss;
     C fe = le - lc;
     C fw = lc - lw;
     C fn = ln - lc;
@@ -94,7 +103,7 @@ __device__ __forceinline__ C hdiff_point(const C *t, C cf) {
     fw = (fw * (uc - uw) > C(0)) ? C(0) : fw;
     fn = (fn * (un - uc) > C(0)) ? C(0) : fn;
     fs = (fs * (uc - us) > C(0)) ? C(0) : fs;
-    return uc - cf * (fe - fw + fn - fs);
+    return fmadd(-cf, fe - fw + fn - fs, uc);
 }
 
 // ---------------------------------------------------------------------------

@@ -11,17 +11,21 @@ namespace stl {
 enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
 
 // Column kernels (column.hpp): register-resident half columns serve
-// nk <= KMAX_COLUMN; (tile_j, prefetch) selects a compiled fused variant.
+// nk <= KMAX_COLUMN.  A fused variant is chosen by rows per workgroup,
+// levels prefetched, non-temporal streams and the level-loop schedule
+// (staged, or pipelined so hdiff of one level overlaps the elimination of an
+// earlier one); only the compiled combinations are accepted.
 constexpr int KMAX_COLUMN = 96;
-bool column_variant_f64(int tile_j, int prefetch, bool nt);
-bool column_variant_f32(int tile_j, int prefetch, bool nt);
-bool column_variant_bf16(int tile_j, int prefetch, bool nt);
-hipError_t launch_column_f64(bool fused, const ColumnArgs &a, int tile_j, int prefetch, bool nt,
-                              hipStream_t st);
-hipError_t launch_column_f32(bool fused, const ColumnArgs &a, int tile_j, int prefetch, bool nt,
-                              hipStream_t st);
-hipError_t launch_column_bf16(bool fused, const ColumnArgs &a, int tile_j, int prefetch, bool nt,
-                              hipStream_t st);
+struct ColumnVariant {
+    int tile_j, prefetch;
+    bool nt, pipe;
+};
+bool column_variant_f64(const ColumnVariant &v);
+bool column_variant_f32(const ColumnVariant &v);
+bool column_variant_bf16(const ColumnVariant &v);
+hipError_t launch_column_f64(bool fused, const ColumnArgs &a, const ColumnVariant &v, hipStream_t st);
+hipError_t launch_column_f32(bool fused, const ColumnArgs &a, const ColumnVariant &v, hipStream_t st);
+hipError_t launch_column_bf16(bool fused, const ColumnArgs &a, const ColumnVariant &v, hipStream_t st);
 
 // Horizontal diffusion alone, inlined, with j-unroll 1, 2 or 4 (hdiff.hip).
 hipError_t launch_hdiff(int dtype, const HdiffArgs &a, int unroll, hipStream_t st);

@@ -141,14 +141,31 @@ def test_config3_full_size(dtype, n):
     assert halo_untouched(x)
 
 
-@pytest.mark.parametrize("tj,pf,nt", [(2, 4, -1), (4, 4, -1), (2, 2, -1), (2, 8, -1), (1, 4, -1),
-                                      (2, 4, 1), (4, 4, 1), (2, 8, 1), (2, 2, 1)])
-def test_fused_variants_are_bitwise_identical(tj, pf, nt):
+@pytest.mark.parametrize("tj,pf,nt,sched", [(2, 4, -1, 1), (4, 4, -1, 1), (2, 2, -1, 1), (2, 8, -1, 1),
+                                            (1, 4, -1, 1), (2, 4, 1, 1), (4, 4, 1, 1), (2, 8, 1, 1),
+                                            (2, 2, 1, 1), (2, 4, 1, 2), (2, 8, 1, 2)])
+def test_fused_variants_are_bitwise_identical(tj, pf, nt, sched):
     ni, nj, nk = 200, 37, 80
     f = inputs.fields(ni, nj, nk, 2, seed=SEED + 4, storage="f32")
     base = run_hdiff_vadv(f, ni, nj, nk, 2, "f32").to_numpy(interior=True)
-    got = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(tile_j=tj, prefetch=pf, nontemporal=nt))
+    cfg = B.config(tile_j=tj, prefetch=pf, nontemporal=nt, schedule=sched)
+    got = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=cfg)
     assert np.array_equal(got.to_numpy(interior=True), base)
+
+
+@pytest.mark.parametrize("nk", [1, 2, 3, 4, 5, 9, 31, 32, 33, 64, 65, 79, 80, 81, 96])
+def test_pipelined_schedule_every_depth(nk):
+    """The pipelined level loop has its own prologue and drain; every column
+    depth, including those shorter than the pipeline, against the staged loop
+    (same arithmetic, so bitwise) and the oracle."""
+    ni, nj = 70, 5
+    f = inputs.fields(ni, nj, nk, 2, seed=SEED + 40 + nk, storage="f32")
+    staged = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(schedule=1)).to_numpy(interior=True)
+    for pf in (4, 8):
+        x = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(prefetch=pf, nontemporal=1, schedule=2))
+        assert np.array_equal(x.to_numpy(interior=True), staged), pf
+        assert halo_untouched(x)
+    assert normwise(staged, ref_hdiff_vadv(f, 2)) <= TOL["f32"]
 
 
 def test_deterministic_and_wider_halo():
