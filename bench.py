@@ -142,6 +142,26 @@ def copy_probe():
     return 2 * nb / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
 
 
+def read_probe():
+    """Achievable HBM read rate (GB/s): the read-only probe over 1 GiB."""
+    import torch
+    from paper_2005_13014_amd import binding as B
+    nb = 1 << 30
+    src = torch.empty(nb // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    sink = torch.zeros(4, dtype=torch.int32, device="cuda")
+    # key 1: all-equal vectors give checksum 0, so the sink is never written
+    for _ in range(3):
+        B.stencil_probe_read(src, nb, 1, sink)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        B.stencil_probe_read(src, nb, 1, sink)
+    e1.record()
+    torch.cuda.synchronize()
+    return nb / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+
+
 def variant_column(ni, nj, nk, dtype, level):
     """Fused (level 0) or unfused 'original' (level 1) program in dtype."""
     import torch
@@ -245,6 +265,100 @@ def cpu_baseline(ni, nj, nk, budget_s=10.0):
                       % (reps, ni, nj, nk, el)}
 
 
+# Profiling commands (run from the repository root $R on the GPU machine) whose
+# output --summarize-profiles turns into the committed summaries.
+TRACE_CMD = ("cd /tmp && TMPDIR=/tmp rocprofv3 --kernel-trace --stats --output-format csv "
+             "-d $R/gpurun_out/prof_trace -o trace -- python $R/bench.py --quick --with-copy "
+             "--steps 20 --warmup 2")
+PMC_CMD = ("cd /tmp && TMPDIR=/tmp timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv "
+           "-d $R/gpurun_out/prof_{t} -o {t} -- python $R/bench.py --quick --with-copy "
+           "--steps 4 --warmup 1")
+COPY_PROBE_BYTES = 1 << 30
+
+
+def summarize_profiles(outdir):
+    """Writes profiles/k_column_f32_512x512x80_trace.md from the kernel trace
+    under outdir/prof_trace and, if the FETCH_SIZE / WRITE_SIZE runs are
+    there, the calibrated traffic summary (JSON + Markdown)."""
+    import csv
+    import glob
+
+    def one(pattern):
+        hits = sorted(glob.glob(os.path.join(outdir, pattern), recursive=True))
+        return hits[0] if hits else None
+
+    def short(name):
+        return name.split("(")[0][:100]
+
+    rows = list(csv.DictReader(open(one("prof_trace/**/*kernel_stats.csv"))))
+    cols = [r for r in rows if "k_column" in r["Name"]]
+    col = max(cols, key=lambda r: float(r["TotalDurationNs"]))
+    kname = short(col["Name"])
+    avg_us = float(col["AverageNs"]) / 1e3
+    ab = fused_bytes(512, 512, 80, 4)
+    out = ["# Kernel trace: fused hdiff+vadv, FP32 512x512x80 (%s)" % kname.split("<")[0].split()[-1],
+           "", "Command (from the repository root `$R` on the GPU box):", "", "```", TRACE_CMD, "```", "",
+           "| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        out.append("| `%s` | %s | %.2f | %.2f | %.2f | %.1f%% |" % (
+            short(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    out += ["", "Headline kernel `%s`: algorithmic bytes per launch %d; at the traced average "
+            "duration %.2f us that is %.1f GB/s (%.1f%% of 8 TB/s).  Kernel sources hash %s." % (
+                kname, ab, avg_us, ab / (avg_us * 1e-6) / 1e9, 100 * ab / (avg_us * 1e-6) / 8e12,
+                kernel_hash())]
+    with open(os.path.join(ROOT, "profiles", "k_column_f32_512x512x80_trace.md"), "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+    def counter(tag, cname):
+        f = one("prof_%s/**/*counter_collection.csv" % tag)
+        per = {}
+        for r in csv.DictReader(open(f)) if f else []:
+            if r.get("Counter_Name") == cname:
+                per.setdefault(short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        return {k: (sum(v) / len(v), len(v)) for k, v in per.items()}
+
+    fetch, write = counter("fetch", "FETCH_SIZE"), counter("write", "WRITE_SIZE")
+    probe = [k for k in fetch if "k_copy16" in k]
+    if kname not in fetch or kname not in write or not probe:
+        print("no matching counter runs; traffic summary not written")
+        return
+    (cf, ncf), (cw, ncw) = fetch[kname], write[kname]
+    pf, pw = fetch[probe[0]][0], write[probe[0]][0]
+    f_fac, w_fac = pf * 1024 / COPY_PROBE_BYTES, pw * 1024 / COPY_PROBE_BYTES
+    fetch_b, write_b = cf * 1024 / f_fac, cw * 1024 / w_fac
+    tot = fetch_b + write_b
+    t = {"kernel": kname, "workload": "fused hdiff+vadv f32 512x512x80 halo 2",
+         "kernel_sources_sha256_16": kernel_hash(),
+         "fetch_kib_per_dispatch": cf, "write_kib_per_dispatch": cw, "dispatches": [ncf, ncw],
+         "copy_probe_fetch_kib": pf, "copy_probe_write_kib": pw,
+         "copy_probe_bytes_each_way": COPY_PROBE_BYTES,
+         "fetch_calibration": f_fac, "write_calibration": w_fac,
+         "hbm_fetch_bytes_per_launch": fetch_b, "hbm_write_bytes_per_launch": write_b,
+         "hbm_bytes_per_launch": tot, "algorithmic_bytes_per_launch": ab,
+         "traffic_over_algorithmic": tot / ab,
+         "commands": [PMC_CMD.format(c="FETCH_SIZE", t="fetch"), PMC_CMD.format(c="WRITE_SIZE", t="write")]}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(t, fh, indent=1)
+    md = ["# HBM traffic of the fused kernel (FP32, 512x512x80, halo 2)", "",
+          "Two counter runs (one counter each), from the repository root `$R` on the GPU box:", "",
+          "```"] + t["commands"] + ["```", "",
+          "`--with-copy` also runs the 1 GiB copy probe (`k_copy16`), which calibrates the counters:", "",
+          "| kernel | FETCH_SIZE (KiB/dispatch) | WRITE_SIZE (KiB/dispatch) |", "|---|---|---|",
+          "| `k_copy16` (1 GiB read, 1 GiB written) | %.0f | %.0f |" % (pf, pw),
+          "| `%s` | %.0f | %.0f |" % (kname, cf, cw), "",
+          "Calibration: FETCH_SIZE reads %.3f of the bytes the copy truly reads, WRITE_SIZE %.3f of the "
+          "bytes it writes.  Scaled, one fused launch moves %.1f MB in and %.1f MB out = %.1f MB against "
+          "%.1f MB algorithmic (u with the ring its stencil reaches, five more inputs, the output): "
+          "**%.3fx**.  Kernel sources hash %s (`bench.py` reports `traffic` only while the sources "
+          "match)." % (f_fac, w_fac, fetch_b / 1e6, write_b / 1e6, tot / 1e6, ab / 1e6, tot / ab,
+                       kernel_hash())]
+    with open(TRAFFIC_FILE[:-5] + ".md", "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,7 +374,13 @@ def main():
                     help="only the headline measurement (no variants, no CPU baseline)")
     ap.add_argument("--with-copy", action="store_true",
                     help="with --quick: also run the copy probe (counter calibration)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write the profile summaries under profiles/ from rocprofv3 output in DIR "
+                         "(no GPU needed)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the stencil path runs on a single MI355X and no "
               "multi-GPU halo exchange is built; run it with --gpus 1", file=sys.stderr)
@@ -315,7 +435,7 @@ def main():
     }
     if args.quick:
         if args.with_copy:
-            log("copy probe %.1f GB/s" % copy_probe())
+            log("copy probe %.1f GB/s, read probe %.1f GB/s" % (copy_probe(), read_probe()))
         print(json.dumps(result), flush=True)
         return
 
@@ -325,7 +445,7 @@ def main():
     result["error_vs_fp64_oracle"] = errors(sets[0][0], sets[0][1]["x"])
     del sets
     torch.cuda.empty_cache()
-    variants = {"copy_probe_GBs": copy_probe()}
+    variants = {"copy_probe_GBs": copy_probe(), "read_probe_GBs": read_probe()}
     torch.cuda.empty_cache()
     for label, dt_, level in (("fused_f64", "f64", 0), ("original_f64", "f64", 1),
                               ("fused_bf16", "bf16", 0)):

@@ -101,7 +101,10 @@ typedef struct {
     int32_t schedule; /* level loop of the fused kernel: 1 staged (each level
                          is staged, evaluated and eliminated in turn), 2
                          pipelined (hdiff of level s overlaps the elimination
-                         of level s-2), 0 the library's choice */
+                         of level s-2), 3 pipelined on a persistent grid (a
+                         workgroup walks several tiles and requests the next
+                         tile's first levels before storing the current
+                         one), 0 the library's choice */
 } stencil_config_t;
 
 /* Horizontal diffusion, per level k and interior point (i, j):
@@ -225,6 +228,13 @@ void stencil_shutdown(void);
  * aligned) from src to dst with a plain streaming kernel.  Measures the
  * achievable HBM copy rate that the stencil kernels are compared against. */
 int stencil_probe_copy(const void *src, void *dst, int64_t nbytes, void *stream);
+
+/* Bandwidth probe: reads nbytes (a multiple of 16, src 16-byte aligned) and
+ * folds them into per-lane XOR checksums; writes one 32-bit word (the
+ * checksum) to sink only if the checksum of some lane equals key (pass a key
+ * the data cannot produce: then nothing is written).  Measures the achievable
+ * HBM read rate. */
+int stencil_probe_read(const void *src, int64_t nbytes, uint32_t key, void *sink, void *stream);
 
 #ifdef __cplusplus
 }

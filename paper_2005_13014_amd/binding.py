@@ -80,6 +80,7 @@ _SIGNATURES = {
     "stencil_abi_version": [],
     "stencil_shutdown": [],
     "stencil_probe_copy": [_V, _V, ctypes.c_int64, _V],
+    "stencil_probe_read": [_V, ctypes.c_int64, ctypes.c_uint32, _V, _V],
 }
 EXPORTS = tuple(_SIGNATURES)
 
@@ -266,6 +267,11 @@ class ProgramSpec:
 def stencil_probe_copy(src, dst, nbytes, stream=None):
     _check(lib().stencil_probe_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                                     int(nbytes), _stream(stream)))
+
+
+def stencil_probe_read(src, nbytes, key, sink, stream=None):
+    _check(lib().stencil_probe_read(ctypes.c_void_p(src.data_ptr()), int(nbytes), int(key),
+                                    ctypes.c_void_p(sink.data_ptr()), _stream(stream)))
 
 
 def stencil_last_error():

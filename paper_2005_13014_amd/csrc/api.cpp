@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -231,25 +232,25 @@ static bool column_variant(int dtype, const ColumnVariant &v) {
 
 // Resolves the fused variant from the knobs; zero knobs take the fastest
 // variant measured at 512 x 512 x 80 (FP32: two rows of 64 columns per half,
-// eight levels prefetched, non-temporal streams).  A non-zero knob that names
-// no compiled variant is an error, not a silent substitution.
+// four levels prefetched, non-temporal streams, pipelined schedule).  A
+// non-zero knob that names no compiled variant is an error, not a silent
+// substitution.
 static int fused_variant(int dtype, const stencil_config_t &cf, ColumnVariant *out) {
     ColumnVariant v{};
     v.tile_j = cf.tile_j ? cf.tile_j : 2;
-    v.prefetch = cf.prefetch ? cf.prefetch : dtype == STENCIL_F64 ? 2 : dtype == STENCIL_F32 ? 8 : 4;
+    v.prefetch = cf.prefetch ? cf.prefetch : dtype == STENCIL_F64 ? 2 : 4;
     if (cf.nontemporal < -1 || cf.nontemporal > 1)
         return fail(STENCIL_E_ARG, "nontemporal must be -1, 0 or 1 (got %d)", cf.nontemporal);
-    if (cf.schedule < 0 || cf.schedule > 2)
-        return fail(STENCIL_E_ARG, "schedule must be 0, 1 or 2 (got %d)", cf.schedule);
+    if (cf.schedule < 0 || cf.schedule > 3)
+        return fail(STENCIL_E_ARG, "schedule must be 0, 1, 2 or 3 (got %d)", cf.schedule);
     const bool nts[2] = {true, false};
-    const bool pipes[2] = {false, true};
+    const int order[3] = {SCHED_PIPELINED, SCHED_PERSISTENT, SCHED_STAGED};  // library preference
     bool found = false;
     for (int q = 0; q < 2 && !found; ++q) {
         v.nt = nts[q];
         if ((cf.nontemporal > 0 && !v.nt) || (cf.nontemporal < 0 && v.nt)) continue;
-        for (int r = 0; r < 2 && !found; ++r) {
-            v.pipe = pipes[r];
-            if ((cf.schedule == 1 && v.pipe) || (cf.schedule == 2 && !v.pipe)) continue;
+        for (int r = 0; r < 3 && !found; ++r) {
+            v.sched = cf.schedule ? cf.schedule : order[r];
             found = column_variant(dtype, v);
         }
     }
@@ -259,6 +260,27 @@ static int fused_variant(int dtype, const stencil_config_t &cf, ColumnVariant *o
                     v.prefetch, cf.nontemporal, cf.schedule);
     *out = v;
     return STENCIL_OK;
+}
+
+// Resident workgroups of `kernel` with `block` threads on the current
+// device: occupancy per CU (cached per kernel) times the CU count (cached per
+// device).  0 if the runtime cannot say.
+int resident_workgroups(const void *kernel, int block) {
+    static std::mutex mu;
+    static std::unordered_map<const void *, int> per_cu;
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!cus[dev] && hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus[dev] = 0;
+    auto it = per_cu.find(kernel);
+    if (it == per_cu.end()) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, 0) != hipSuccess) nb = 0;
+        it = per_cu.emplace(kernel, nb).first;
+    }
+    return it->second * cus[dev];
 }
 
 // Column kernels address every field through a raw buffer of < 2^31 bytes.
@@ -447,4 +469,13 @@ STENCIL_API int stencil_probe_copy(const void *src, void *dst, int64_t nbytes, v
     if (s < d + nbytes && d < s + nbytes) return fail(STENCIL_E_ALIAS, "probe_copy: ranges overlap");
     return launch_status(launch_probe_copy(src, dst, nbytes, static_cast<hipStream_t>(stream)),
                          "copy kernel");
+}
+
+STENCIL_API int stencil_probe_read(const void *src, int64_t nbytes, uint32_t key, void *sink, void *stream) {
+    if (!src || !sink) return fail(STENCIL_E_NULL, "probe_read: NULL pointer");
+    if (nbytes < 0 || nbytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 ||
+        reinterpret_cast<uintptr_t>(sink) % 4)
+        return fail(STENCIL_E_ARG, "probe_read: nbytes and src must be 16-byte aligned, sink 4-byte");
+    return launch_status(launch_probe_read(src, nbytes, key, sink, static_cast<hipStream_t>(stream)),
+                         "read kernel");
 }

@@ -175,13 +175,19 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
         static_cast<uint32_t>(min(i0 - 2 + sc, I + 1) + 2 + (min(j0 - 2 + sr, J + 1) + 2) * sj) * ES;
     const int lside = l < 4 * PJ ? sr * PI + sc : PJ * PI + ti;
 
-    const int M = EXACT ? KH : (K + 1) >> 1;
+    // Both halves run KH steps.  A half with nsteps < KH levels starts with
+    // shift = KH - nsteps padding steps: identity rows (b = 1, upper = 0,
+    // zero right-hand side, no flux through their faces) that leave the
+    // elimination of the real rows unchanged; step s holds local level
+    // s - shift.  The loop has no run-time guards (EXACT: shift = 0).
+    const int M = (K + 1) >> 1;
     const int nsteps = EXACT ? KH : half ? K - M : M;
-    auto level = [&](int s) { return half ? (EXACT ? 2 * KH : K) - 1 - s : s; };
+    const int shift = EXACT ? 0 : KH - nsteps;
+    auto level = [&](int t) { return half ? (EXACT ? 2 * KH : K) - 1 - t : t; };
 
     C rum[PF][FUSED ? MR : 1], rus[PF], rcfv[PF], rwv[PF], rlov[PF], rbv[PF], rupv[PF];
-    auto load = [&](int q, int s) {
-        const uint32_t so = static_cast<uint32_t>(level(s)) * sk_bytes;
+    auto load = [&](int q, int s) {  // inputs of step s (padding steps re-read level 0)
+        const uint32_t so = static_cast<uint32_t>(level(max(s - shift, 0))) * sk_bytes;
         if constexpr (FUSED) {
 #pragma unroll
             for (int m = 0; m < MR; ++m) rum[q][m] = IO::load(ru, vmain[m], so);
@@ -196,8 +202,7 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
         rupv[q] = IO::template load<CP>(rup, vcol, so);
     };
 #pragma unroll
-    for (int q = 0; q < PF; ++q)
-        if (q < nsteps) load(q, q);
+    for (int q = 0; q < PF && q < KH; ++q) load(q, q);
 
     // d(prev) = h(prev) - dt (F above - F below).  Half 0 walks up (the new
     // face is above the previous level), half 1 walks down (it is below), so
@@ -206,62 +211,60 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     C h_prev = C(0), w_prev = C(0), f_old = C(0);
     double lo_prev = 0.0, b_prev = 1.0, up_prev = 0.0;
     double P[KH], D[KH];
-    double P_last = 0.0, D_last = 0.0;  // row t - 1 of the running elimination
 
 #pragma unroll
     for (int s = 0; s < KH; ++s) {
-        if (s < M) {
-            const bool on = s < nsteps;
-            const int q = s % PF;
-            C *tb = &tile[(half * 2 + (s & 1)) * TILE];
-            if constexpr (FUSED) {
-                if (on) {
+        const int q = s % PF;
+        C *tb = &tile[(half * 2 + (s & 1)) * TILE];
+        if constexpr (FUSED) {
 #pragma unroll
-                    for (int m = 0; m < MR; ++m) tb[lmain[m]] = rum[q][m];
-                    if (side_wave) tb[lside] = rus[q];
-                }
-            }
-            const C hv = FUSED ? C(0) : rum[q][0];
-            const C cf = FUSED ? rcfv[q] : C(0);
-            const C wv = rwv[q];
-            const double lov = static_cast<double>(rlov[q]), bv = static_cast<double>(rbv[q]),
-                         upv = static_cast<double>(rupv[q]);
-            if (s + PF < nsteps) load(q, s + PF);
-            if constexpr (FUSED) __syncthreads();
-            if (on) {
-                const C h = FUSED ? hdiff_point<C, PI>(tb + (tj + 2) * PI + ti + 2, cf) : hv;
-                if (s > 0) {
-                    // Face between the previous and this level; right-hand side
-                    // and elimination of the previous level.
-                    const C f_new = (C(0.5) * (w_prev + wv)) * (C(0.5) * (h_prev + h));
-                    const double d = static_cast<double>(fmadd(-dts, f_new - f_old, h_prev));
-                    const int tt = s > 0 ? s - 1 : 0;
-                    if (tt == 0) {
-                        const double r = recip(b_prev);
-                        P[0] = up_prev * r;
-                        D[0] = d * r;
-                    } else {
-                        const int tm = tt > 0 ? tt - 1 : 0;
-                        const double r = recip(fmadd(-lo_prev, P[tm], b_prev));
-                        P[tt] = up_prev * r;
-                        D[tt] = fmadd(-lo_prev, D[tm], d) * r;
-                    }
-                    if constexpr (EXACT) {
-                        pin(P[tt]);
-                        pin(D[tt]);
-                    }
-                    P_last = P[tt];
-                    D_last = D[tt];
-                    f_old = f_new;
-                }
-                h_prev = h;
-                w_prev = wv;
-                lo_prev = lov;
-                up_prev = upv;
-                b_prev = bv;
-            }
+            for (int m = 0; m < MR; ++m) tb[lmain[m]] = rum[q][m];
+            if (side_wave) tb[lside] = rus[q];
         }
+        const C hv = FUSED ? C(0) : rum[q][0];
+        const C cf = FUSED ? rcfv[q] : C(0);
+        const C wv = rwv[q];
+        const double lov = static_cast<double>(rlov[q]), bv = static_cast<double>(rbv[q]),
+                     upv = static_cast<double>(rupv[q]);
+        if (s + PF < KH) load(q, s + PF);
+        if constexpr (FUSED) __syncthreads();
+        const C h = FUSED ? hdiff_point<C, PI>(tb + (tj + 2) * PI + ti + 2, cf) : hv;
+        if (s > 0) {
+            // Face between the previous and this step's level; right-hand
+            // side and elimination of the previous level (row tt).
+            const int tt = s > 0 ? s - 1 : 0;
+            const bool pad = tt < shift;
+            C f_new = (C(0.5) * (w_prev + wv)) * (C(0.5) * (h_prev + h));
+            if (pad) f_new = C(0);
+            double d = static_cast<double>(fmadd(-dts, f_new - f_old, h_prev));
+            double bt = b_prev, upt = up_prev;
+            if (pad) {
+                d = 0.0;
+                bt = 1.0;
+                upt = 0.0;
+            }
+            if (tt == 0) {
+                const double r = recip(bt);
+                P[0] = upt * r;
+                D[0] = d * r;
+            } else {
+                const int tm = tt > 0 ? tt - 1 : 0;
+                const double r = recip(fmadd(-lo_prev, P[tm], bt));
+                P[tt] = upt * r;
+                D[tt] = fmadd(-lo_prev, D[tm], d) * r;
+            }
+            pin(P[tt]);
+            pin(D[tt]);
+            f_old = f_new;
+        }
+        h_prev = h;
+        w_prev = wv;
+        lo_prev = lov;
+        up_prev = upv;
+        b_prev = bv;
     }
+    const double P_last = KH > 1 ? P[KH > 1 ? KH - 2 : 0] : 0.0;
+    const double D_last = KH > 1 ? D[KH > 1 ? KH - 2 : 0] : 0.0;
 
     // Interface, part 1: the face between levels M-1 and M.
     xch[tid] = make_double2(static_cast<double>(h_prev), static_cast<double>(w_prev));
@@ -286,24 +289,25 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     const double P0 = half ? o2.x : Pm, D0 = half ? o2.y : Dm;
     const double P1 = half ? Pm : o2.x, D1 = half ? Dm : o2.y;
     const double x_lo = fmadd(-P0, D1, D0) / fmadd(-P0, P1, 1.0);  // x(M-1)
-    const double x_hi = fmadd(-P1, x_lo, D1);                     // x(M)
+    const double x_hi = fmadd(-P1, x_lo, D1);                      // x(M)
 
-    // Back-substitution outward from the interface.  Local index t counts
-    // from the far end of this half's levels (level(t)); the walk runs from
-    // t = nsteps - 1 (the interface) down to t = 0.
+    // Back-substitution outward from the interface.  Row tt of the
+    // elimination is local level tt - shift; the walk runs from the
+    // interface (local level nsteps - 1) down to local level 0.
     double xn = half ? x_hi : x_lo;
     if constexpr (!VDIFF) {
         if (active && nsteps > 0)
             IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, xn);
 #pragma unroll
         for (int tt = KH - 2; tt >= 0; --tt) {
-            if (tt < nsteps - 1) {
+            if (tt >= shift) {
                 xn = fmadd(-P[tt], xn, D[tt]);
-                if (active) IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(tt)) * sk_bytes, xn);
+                if (active)
+                    IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(tt - shift)) * sk_bytes, xn);
             }
         }
     } else {
-        // y at local index t + 1 is finished once x(t) is known: its neighbour
+        // y at local level t + 1 is finished once x(t) is known: its neighbour
         // toward the interface is x(t + 2) (the other half's interface value
         // for t + 1 = nsteps - 1), away from it x(t).  Half 0 walks down
         // (toward = up), half 1 walks up (toward = down).
@@ -320,9 +324,10 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
         };
 #pragma unroll
         for (int tt = KH - 2; tt >= 0; --tt) {
-            if (tt < nsteps - 1) {
+            if (tt >= shift) {
+                const int t = tt - shift;
                 const double xt = fmadd(-P[tt], x_cur, D[tt]);
-                finish(tt + 1, x_in, tt + 1 < nsteps - 1 || has_other, xt, true);
+                finish(t + 1, x_in, t + 1 < nsteps - 1 || has_other, xt, true);
                 x_in = x_cur;
                 x_cur = xt;
             }
@@ -337,8 +342,14 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
 // staged one step earlier; form d(s-1); eliminate level s-2, whose inputs were
 // ready a step ago, so its double-precision chain is independent of this
 // step's hdiff and the two interleave; one barrier closes the step.
-template <class T, int TJ, int PF, int KH, bool NT, bool EXACT>
-__device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int bi, int bj) {
+//
+// A workgroup walks the tiles first, first + stride, ... below ntiles.  With
+// a persistent grid (stride = resident workgroups) the first PF levels of the
+// next tile are requested before the current tile's back-substitution, so
+// their latency hides behind the output stores instead of opening each tile
+// with an idle wait.  A one-shot grid passes stride = ntiles.
+template <class T, int TJ, int PF, int KH, bool NT, bool EXACT, bool CHAIN>
+__device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int first, int stride, int ntiles) {
 #pragma clang fp contract(off)
     using S = Storage<T>;
     using C = typename S::C;
@@ -355,11 +366,7 @@ __device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int bi, in
     const int half = __builtin_amdgcn_readfirstlane(tid >= NH ? 1 : 0);
     const int l = tid - half * NH, ti = l & 63;
     const int tj = __builtin_amdgcn_readfirstlane(l >> 6);
-    const int i0 = bi * TI, j0 = bj * TJ;
-    const int gi = i0 + ti, gj = j0 + tj;
-    const bool active = gi < p.I && gj < p.J;
     const int I = p.I, J = p.J, K = p.K, sj = p.sj;
-    const uint32_t vcol = static_cast<uint32_t>(min(gi, I - 1) + min(gj, J - 1) * sj) * ES;
     const uint32_t sk_bytes = static_cast<uint32_t>(p.sk) * ES;
 
     const auto ru = make_rsrc(p.u, p.u_bytes);
@@ -370,29 +377,38 @@ __device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int bi, in
     const auto rup = make_rsrc(half ? p.a : p.c, p.col_bytes);
     const auto rx = make_rsrc(p.x, p.col_bytes);
 
-    uint32_t vmain[MR];
     int lmain[MR];
 #pragma unroll
-    for (int m = 0; m < MR; ++m) {
-        const int r = tj + m * TJ;
-        const int gx = min(gi, I + 1), gy = min(j0 - 2 + r, J + 1);
-        vmain[m] = static_cast<uint32_t>(gx + 2 + (gy + 2) * sj) * ES;
-        lmain[m] = r * PI + ti + 2;
-    }
+    for (int m = 0; m < MR; ++m) lmain[m] = (tj + m * TJ) * PI + ti + 2;
     const bool side_wave = tj == 0;
     const int sr = min(l >> 2, PJ - 1), sq = l & 3;
     const int sc = sq < 2 ? sq : sq + 64;
-    const uint32_t vside =
-        static_cast<uint32_t>(min(i0 - 2 + sc, I + 1) + 2 + (min(j0 - 2 + sr, J + 1) + 2) * sj) * ES;
     const int lside = l < 4 * PJ ? sr * PI + sc : PJ * PI + ti;
 
-    const int M = EXACT ? KH : (K + 1) >> 1;
+    // Per-tile lane offsets (bytes from each field's interior origin).
+    uint32_t vmain[MR], vside = 0, vcol = 0;
+    bool active = false;
+    auto locate = [&](int t) {
+        const int i0 = (t % p.nbi) * TI, j0 = (t / p.nbi) * TJ;
+        const int gi = i0 + ti, gj = j0 + tj;
+        active = gi < I && gj < J;
+        vcol = static_cast<uint32_t>(min(gi, I - 1) + min(gj, J - 1) * sj) * ES;
+#pragma unroll
+        for (int m = 0; m < MR; ++m) {
+            const int gx = min(gi, I + 1), gy = min(j0 - 2 + tj + m * TJ, J + 1);
+            vmain[m] = static_cast<uint32_t>(gx + 2 + (gy + 2) * sj) * ES;
+        }
+        vside = static_cast<uint32_t>(min(i0 - 2 + sc, I + 1) + 2 + (min(j0 - 2 + sr, J + 1) + 2) * sj) * ES;
+    };
+
+    const int M = (K + 1) >> 1;
     const int nsteps = EXACT ? KH : half ? K - M : M;
-    auto level = [&](int s) { return half ? (EXACT ? 2 * KH : K) - 1 - s : s; };
+    const int shift = EXACT ? 0 : KH - nsteps;  // leading identity rows, as in column_tile
+    auto level = [&](int t) { return half ? (EXACT ? 2 * KH : K) - 1 - t : t; };
 
     C rum[PF][MR], rus[PF], rcfv[PF], rwv[PF], rlov[PF], rbv[PF], rupv[PF];
     auto load = [&](int q, int s) {
-        const uint32_t so = static_cast<uint32_t>(level(s)) * sk_bytes;
+        const uint32_t so = static_cast<uint32_t>(level(max(s - shift, 0))) * sk_bytes;
 #pragma unroll
         for (int m = 0; m < MR; ++m) rum[q][m] = IO::load(ru, vmain[m], so);
         if (side_wave) rus[q] = IO::load(ru, vside, so);
@@ -402,10 +418,10 @@ __device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int bi, in
         rbv[q] = IO::template load<CP>(rb, vcol, so);
         rupv[q] = IO::template load<CP>(rup, vcol, so);
     };
-    // Column values of the level whose hdiff comes next ("cur").
+    // Column values of the step whose hdiff comes next ("cur").
     C cf_c = C(0), w_c = C(0);
     double lo_c = 0.0, b_c = 1.0, up_c = 0.0;
-    auto stage = [&](int s) {  // tile and column values of level s from the ring
+    auto stage = [&](int s) {  // tile and column values of step s from the ring
         const int q = s % PF;
         C *tb = &tile[(half * 3 + s % 3) * TILE];
 #pragma unroll
@@ -416,135 +432,145 @@ __device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int bi, in
         lo_c = static_cast<double>(rlov[q]);
         b_c = static_cast<double>(rbv[q]);
         up_c = static_cast<double>(rupv[q]);
-        if (s + PF < nsteps) load(q, s + PF);
+        if (s + PF < KH) load(q, s + PF);
     };
 
-#pragma unroll
-    for (int q = 0; q < PF; ++q)
-        if (q < nsteps) load(q, q);
-    if (nsteps > 0) stage(0);
-    __syncthreads();
-
     const C dts = half ? -static_cast<C>(p.dt) : static_cast<C>(p.dt);
-    C h_prev = C(0), w_prev = C(0), f_old = C(0);
-    double lo_prev = 0.0, b_prev = 1.0, up_prev = 0.0;           // level s-1
-    double d_pend = 0.0, lo_pend = 0.0, b_pend = 1.0, up_pend = 0.0;  // level s-2
     double P[KH], D[KH];
-    double P_last = 0.0, D_last = 0.0;
-
-#pragma unroll
-    for (int s = 0; s <= KH; ++s) {
-        if (s >= 2 && s == nsteps) {
-            // Past the last step: eliminate the level before the last, the
-            // one the last step left pending.
-            const int t = s >= 2 ? s - 2 : 0;
-            if (t == 0) {
-                const double r = recip(b_pend);
-                P[0] = up_pend * r;
-                D[0] = d_pend * r;
-            } else {
-                const int tm = t > 0 ? t - 1 : 0;
-                const double r = recip(fmadd(-lo_pend, P[tm], b_pend));
-                P[t] = up_pend * r;
-                D[t] = fmadd(-lo_pend, D[tm], d_pend) * r;
-            }
-            P_last = P[t];
-            D_last = D[t];
+    double d_pend = 0.0, lo_pend = 0.0, b_pend = 1.0, up_pend = 0.0;  // row s-2
+    auto eliminate = [&](int t) {  // row t from the pending values
+        if (t == 0) {
+            const double r = recip(b_pend);
+            P[0] = up_pend * r;
+            D[0] = d_pend * r;
+        } else {
+            const int tm = t > 0 ? t - 1 : 0;
+            const double r = recip(fmadd(-lo_pend, P[tm], b_pend));
+            P[t] = up_pend * r;
+            D[t] = fmadd(-lo_pend, D[tm], d_pend) * r;
         }
-        if (s < M) {
-            if (s < nsteps) {
-                // Values of level s (staged one step ago) before the next stage overwrites them.
-                const C cf = cf_c, wv = w_c;
-                const double lov = lo_c, bv = b_c, upv = up_c;
-                if (s + 1 < nsteps) stage(s + 1);
-                const C *tb = &tile[(half * 3 + s % 3) * TILE];
-                const C h = hdiff_point<C, PI>(tb + (tj + 2) * PI + ti + 2, cf);
-                if (s >= 2) {
-                    const int t = s >= 2 ? s - 2 : 0;
-                    if (t == 0) {
-                        const double r = recip(b_pend);
-                        P[0] = up_pend * r;
-                        D[0] = d_pend * r;
-                    } else {
-                        const int tm = t > 0 ? t - 1 : 0;
-                        const double r = recip(fmadd(-lo_pend, P[tm], b_pend));
-                        P[t] = up_pend * r;
-                        D[t] = fmadd(-lo_pend, D[tm], d_pend) * r;
-                    }
-                    if constexpr (EXACT) {
-                        pin(P[t]);
-                        pin(D[t]);
-                    }
-                    P_last = P[t];
-                    D_last = D[t];
+        pin(P[t]);
+        pin(D[t]);
+    };
+
+    int t = first;
+    if (t >= ntiles) return;
+    locate(t);
+#pragma unroll
+    for (int q = 0; q < PF && q < KH; ++q) load(q, q);
+
+    for (;;) {
+        stage(0);
+        __syncthreads();
+        C h_prev = C(0), w_prev = C(0), f_old = C(0);
+        double lo_prev = 0.0, b_prev = 1.0, up_prev = 0.0;  // step s-1
+#pragma unroll
+        for (int s = 0; s < KH; ++s) {
+            // Values of step s (staged one step ago) before the next stage overwrites them.
+            const C cf = cf_c, wv = w_c;
+            const double lov = lo_c, bv = b_c, upv = up_c;
+            if (s + 1 < KH) stage(s + 1);
+            const C *tb = &tile[(half * 3 + s % 3) * TILE];
+            const C h = hdiff_point<C, PI>(tb + (tj + 2) * PI + ti + 2, cf);
+            if (s >= 2) eliminate(s >= 2 ? s - 2 : 0);
+            if (s >= 1) {
+                const bool pad = s - 1 < shift;
+                C f_new = (C(0.5) * (w_prev + wv)) * (C(0.5) * (h_prev + h));
+                if (pad) f_new = C(0);
+                d_pend = static_cast<double>(fmadd(-dts, f_new - f_old, h_prev));
+                f_old = f_new;
+                lo_pend = lo_prev;
+                b_pend = b_prev;
+                up_pend = up_prev;
+                if (pad) {
+                    d_pend = 0.0;
+                    b_pend = 1.0;
+                    up_pend = 0.0;
                 }
-                if (s >= 1) {
-                    const C f_new = (C(0.5) * (w_prev + wv)) * (C(0.5) * (h_prev + h));
-                    d_pend = static_cast<double>(fmadd(-dts, f_new - f_old, h_prev));
-                    f_old = f_new;
-                    lo_pend = lo_prev;
-                    b_pend = b_prev;
-                    up_pend = up_prev;
-                }
-                h_prev = h;
-                w_prev = wv;
-                lo_prev = lov;
-                b_prev = bv;
-                up_prev = upv;
             }
+            h_prev = h;
+            w_prev = wv;
+            lo_prev = lov;
+            b_prev = bv;
+            up_prev = upv;
             __syncthreads();
         }
-    }
-    // Interface, part 1: the face between levels M-1 and M.
-    xch[tid] = make_double2(static_cast<double>(h_prev), static_cast<double>(w_prev));
-    __syncthreads();
-    const double2 o1 = xch[half ? l : NH + l];
-    C f_mid = C(0);
-    if (K - M > 0)
-        f_mid = (C(0.5) * (w_prev + static_cast<C>(o1.y))) * (C(0.5) * (h_prev + static_cast<C>(o1.x)));
-    double Pm = 0.0, Dm = 0.0;
-    if (nsteps > 0) {
-        const double d = static_cast<double>(fmadd(-dts, f_mid - f_old, h_prev));
-        const double m = nsteps > 1 ? fmadd(-lo_prev, P_last, b_prev) : b_prev;
-        const double r = recip(m);
-        Pm = up_prev * r;
-        Dm = (nsteps > 1 ? fmadd(-lo_prev, D_last, d) : d) * r;
-    }
-    __syncthreads();
-    xch[tid] = make_double2(Pm, Dm);
-    __syncthreads();
-    const double2 o2 = xch[half ? l : NH + l];
-    const double P0 = half ? o2.x : Pm, D0 = half ? o2.y : Dm;
-    const double P1 = half ? Pm : o2.x, D1 = half ? Dm : o2.y;
-    const double x_lo = fmadd(-P0, D1, D0) / fmadd(-P0, P1, 1.0);
-    const double x_hi = fmadd(-P1, x_lo, D1);
+        // The last step left row KH - 2 pending.
+        if (KH >= 2) eliminate(KH >= 2 ? KH - 2 : 0);
+        const double P_last = KH > 1 ? P[KH > 1 ? KH - 2 : 0] : 0.0;
+        const double D_last = KH > 1 ? D[KH > 1 ? KH - 2 : 0] : 0.0;
 
-    double xn = half ? x_hi : x_lo;
-    if (active && nsteps > 0)
-        IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, xn);
-#pragma unroll
-    for (int tt = KH - 2; tt >= 0; --tt) {
-        if (tt < nsteps - 1) {
-            xn = fmadd(-P[tt], xn, D[tt]);
-            if (active) IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(tt)) * sk_bytes, xn);
+        // Interface, part 1: the face between levels M-1 and M.
+        xch[tid] = make_double2(static_cast<double>(h_prev), static_cast<double>(w_prev));
+        __syncthreads();
+        const double2 o1 = xch[half ? l : NH + l];
+        C f_mid = C(0);
+        if (K - M > 0)
+            f_mid = (C(0.5) * (w_prev + static_cast<C>(o1.y))) * (C(0.5) * (h_prev + static_cast<C>(o1.x)));
+        double Pm = 0.0, Dm = 0.0;
+        if (nsteps > 0) {
+            const double d = static_cast<double>(fmadd(-dts, f_mid - f_old, h_prev));
+            const double m = nsteps > 1 ? fmadd(-lo_prev, P_last, b_prev) : b_prev;
+            const double r = recip(m);
+            Pm = up_prev * r;
+            Dm = (nsteps > 1 ? fmadd(-lo_prev, D_last, d) : d) * r;
         }
+        __syncthreads();
+        xch[tid] = make_double2(Pm, Dm);
+        __syncthreads();
+        const double2 o2 = xch[half ? l : NH + l];
+        const double P0 = half ? o2.x : Pm, D0 = half ? o2.y : Dm;
+        const double P1 = half ? Pm : o2.x, D1 = half ? Dm : o2.y;
+        const double x_lo = fmadd(-P0, D1, D0) / fmadd(-P0, P1, 1.0);
+        const double x_hi = fmadd(-P1, x_lo, D1);
+
+        // Request the next tile's first levels, then store this one.
+        const uint32_t vx = vcol;
+        const bool store = active;
+        const int tn = t + stride;
+        const bool more = CHAIN && tn < ntiles;
+        if (more) {
+            locate(tn);
+#pragma unroll
+            for (int q = 0; q < PF && q < KH; ++q) load(q, q);
+        }
+        double xn = half ? x_hi : x_lo;
+        if (store && nsteps > 0)
+            IO::template store_d<CP>(rx, vx, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, xn);
+#pragma unroll
+        for (int tt = KH - 2; tt >= 0; --tt) {
+            if (tt >= shift) {
+                xn = fmadd(-P[tt], xn, D[tt]);
+                if (store) IO::template store_d<CP>(rx, vx, static_cast<uint32_t>(level(tt - shift)) * sk_bytes, xn);
+            }
+        }
+        if (!more) break;
+        t = tn;
     }
 }
 
-template <class T, int TJ, int PF, int KH, int WPE, bool NT, bool EXACT>
+template <class T, int TJ, int PF, int KH, int WPE, bool NT, bool EXACT, bool CHAIN>
 __global__ __launch_bounds__(128 * TJ) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void
-k_column_pipe(ColumnArgs p) {
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    column_tile_pipe<T, TJ, PF, KH, NT, EXACT>(p, t % p.nbi, t / p.nbi);
+k_column_pipe(ColumnArgs p, int ntiles) {
+    // Consecutive tile positions share an XCD (and its L2) in every round.
+    column_tile_pipe<T, TJ, PF, KH, NT, EXACT, CHAIN>(p, xcd_tile(blockIdx.x, gridDim.x), gridDim.x, ntiles);
 }
 
-template <class T, int TJ, int PF, int KH, int WPE, bool NT, bool EXACT = false>
+// CHAIN: a persistent grid of resident workgroups walks the tiles; otherwise
+// one workgroup per tile.
+template <class T, int TJ, int PF, int KH, int WPE, bool NT, bool EXACT = false, bool CHAIN = false>
 static hipError_t launch_column_pipe_t(ColumnArgs a, hipStream_t st) {
-    if (EXACT && a.K != 2 * KH) return hipErrorInvalidValue;
+    if ((EXACT && a.K != 2 * KH) || (a.K + 1) / 2 > KH) return hipErrorInvalidValue;
     a.nbi = (a.I + 63) / 64;
     a.nbj = (a.J + TJ - 1) / TJ;
-    hipLaunchKernelGGL((k_column_pipe<T, TJ, PF, KH, WPE, NT, EXACT>), dim3(a.nbi * a.nbj), dim3(128 * TJ),
-                       0, st, a);
+    const int ntiles = a.nbi * a.nbj;
+    auto kern = k_column_pipe<T, TJ, PF, KH, WPE, NT, EXACT, CHAIN>;
+    int grid = ntiles;
+    if (CHAIN) {
+        const int res = resident_workgroups(reinterpret_cast<const void *>(kern), 128 * TJ);
+        if (res > 0 && res < grid) grid = res;
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(128 * TJ), 0, st, a, ntiles);
     return hipGetLastError();
 }
 
@@ -600,7 +626,7 @@ k_column_batch(ColumnBatch b) {
 // ---------------------------------------------------------------------------
 template <class T, bool FUSED, int TJ, int PF, int KH, int WPE, bool NT = false, bool EXACT = false>
 static hipError_t launch_column_t(ColumnArgs a, hipStream_t st) {
-    if (EXACT && a.K != 2 * KH) return hipErrorInvalidValue;
+    if ((EXACT && a.K != 2 * KH) || (a.K + 1) / 2 > KH) return hipErrorInvalidValue;
     a.nbi = (a.I + 63) / 64;
     a.nbj = (a.J + TJ - 1) / TJ;
     hipLaunchKernelGGL((k_column<T, FUSED, TJ, PF, KH, WPE, NT, EXACT>), dim3(a.nbi * a.nbj),
@@ -611,14 +637,15 @@ static hipError_t launch_column_t(ColumnArgs a, hipStream_t st) {
 // A compiled fused variant: its knobs and the launcher of its KH buckets.
 struct ColumnEntry {
     int tile_j, prefetch;
-    bool nt, pipe;
+    bool nt;
+    int sched;
     hipError_t (*launch)(const ColumnArgs &, hipStream_t);
 };
 
 template <int N>
-static const ColumnEntry *find_column_entry(const ColumnEntry (&tab)[N], int tj, int pf, bool nt, bool pipe) {
+static const ColumnEntry *find_column_entry(const ColumnEntry (&tab)[N], int tj, int pf, bool nt, int sched) {
     for (int q = 0; q < N; ++q)
-        if (tab[q].tile_j == tj && tab[q].prefetch == pf && tab[q].nt == nt && tab[q].pipe == pipe)
+        if (tab[q].tile_j == tj && tab[q].prefetch == pf && tab[q].nt == nt && tab[q].sched == sched)
             return &tab[q];
     return nullptr;
 }

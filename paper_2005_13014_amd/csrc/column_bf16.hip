@@ -4,28 +4,35 @@
 
 namespace stl {
 
-// Register-resident half columns of KH levels serve nk <= 2 KH.
+// Register-resident half columns of KH levels serve nk <= 2 KH; a depth
+// that fills its bucket exactly (nk = 2 KH) takes the kernel without
+// padding steps.
 template <bool FUSED, int TJ, int PF, bool NT>
 static hipError_t staged(const ColumnArgs &a, hipStream_t st) {
     const int m = (a.K + 1) / 2;
-    if (m <= 16) return launch_column_t<uint16_t, FUSED, TJ, PF, 16, 2, NT>(a, st);
-    if (m <= 32) return launch_column_t<uint16_t, FUSED, TJ, PF, 32, 2, NT>(a, st);
-    if (m <= 40) return launch_column_t<uint16_t, FUSED, TJ, PF, 40, 2, NT>(a, st);
-    return launch_column_t<uint16_t, FUSED, TJ, PF, 48, 1, NT>(a, st);
+    constexpr bool X = FUSED;
+    if (m <= 16) return X && a.K == 32 ? launch_column_t<uint16_t, FUSED, TJ, PF, 16, 2, NT, X>(a, st)
+                                       : launch_column_t<uint16_t, FUSED, TJ, PF, 16, 2, NT>(a, st);
+    if (m <= 32) return X && a.K == 64 ? launch_column_t<uint16_t, FUSED, TJ, PF, 32, 2, NT, X>(a, st)
+                                       : launch_column_t<uint16_t, FUSED, TJ, PF, 32, 2, NT>(a, st);
+    if (m <= 40) return X && a.K == 80 ? launch_column_t<uint16_t, FUSED, TJ, PF, 40, 2, NT, X>(a, st)
+                                       : launch_column_t<uint16_t, FUSED, TJ, PF, 40, 2, NT>(a, st);
+    return X && a.K == 96 ? launch_column_t<uint16_t, FUSED, TJ, PF, 48, 1, NT, X>(a, st)
+                          : launch_column_t<uint16_t, FUSED, TJ, PF, 48, 1, NT>(a, st);
 }
 
 static const ColumnEntry kFused[] = {
-    {2, 4, false, false, staged<true, 2, 4, false>},
-    {4, 4, false, false, staged<true, 4, 4, false>},
+    {2, 4, false, 1, staged<true, 2, 4, false>},
+    {4, 4, false, 1, staged<true, 4, 4, false>},
 };
 
 bool column_variant_bf16(const ColumnVariant &v) {
-    return find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.pipe) != nullptr;
+    return find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.sched) != nullptr;
 }
 
 hipError_t launch_column_bf16(bool fused, const ColumnArgs &a, const ColumnVariant &v, hipStream_t st) {
     if (!fused) return staged<false, 2, 4, false>(a, st);
-    const ColumnEntry *e = find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.pipe);
+    const ColumnEntry *e = find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.sched);
     return e ? e->launch(a, st) : hipErrorInvalidValue;
 }
 

@@ -4,8 +4,9 @@
 
 namespace stl {
 
-// Register-resident half columns of KH levels serve nk <= 2 KH.
-// Depths that fill a bucket exactly (nk = 2 KH) take a guard-free kernel.
+// Register-resident half columns of KH levels serve nk <= 2 KH; a depth
+// that fills its bucket exactly (nk = 2 KH) takes the kernel without
+// padding steps.
 template <bool FUSED, int TJ, int PF, bool NT>
 static hipError_t staged(const ColumnArgs &a, hipStream_t st) {
     const int m = (a.K + 1) / 2;
@@ -20,40 +21,41 @@ static hipError_t staged(const ColumnArgs &a, hipStream_t st) {
                           : launch_column_t<float, FUSED, TJ, PF, 48, 1, NT>(a, st);
 }
 
-template <int TJ, int PF, bool NT>
+template <int TJ, int PF, bool NT, bool CHAIN>
 static hipError_t pipelined(const ColumnArgs &a, hipStream_t st) {
     const int m = (a.K + 1) / 2;
-    if (m <= 16) return a.K == 32 ? launch_column_pipe_t<float, TJ, PF, 16, 2, NT, true>(a, st)
-                                  : launch_column_pipe_t<float, TJ, PF, 16, 2, NT>(a, st);
-    if (m <= 32) return a.K == 64 ? launch_column_pipe_t<float, TJ, PF, 32, 2, NT, true>(a, st)
-                                  : launch_column_pipe_t<float, TJ, PF, 32, 2, NT>(a, st);
-    if (m <= 40) return a.K == 80 ? launch_column_pipe_t<float, TJ, PF, 40, 2, NT, true>(a, st)
-                                  : launch_column_pipe_t<float, TJ, PF, 40, 2, NT>(a, st);
-    return a.K == 96 ? launch_column_pipe_t<float, TJ, PF, 48, 1, NT, true>(a, st)
-                     : launch_column_pipe_t<float, TJ, PF, 48, 1, NT>(a, st);
+    if (m <= 16) return a.K == 32 ? launch_column_pipe_t<float, TJ, PF, 16, 2, NT, true, CHAIN>(a, st)
+                                  : launch_column_pipe_t<float, TJ, PF, 16, 2, NT, false, CHAIN>(a, st);
+    if (m <= 32) return a.K == 64 ? launch_column_pipe_t<float, TJ, PF, 32, 2, NT, true, CHAIN>(a, st)
+                                  : launch_column_pipe_t<float, TJ, PF, 32, 2, NT, false, CHAIN>(a, st);
+    if (m <= 40) return a.K == 80 ? launch_column_pipe_t<float, TJ, PF, 40, 2, NT, true, CHAIN>(a, st)
+                                  : launch_column_pipe_t<float, TJ, PF, 40, 2, NT, false, CHAIN>(a, st);
+    return a.K == 96 ? launch_column_pipe_t<float, TJ, PF, 48, 1, NT, true, CHAIN>(a, st)
+                     : launch_column_pipe_t<float, TJ, PF, 48, 1, NT, false, CHAIN>(a, st);
 }
 
 static const ColumnEntry kFused[] = {
-    {2, 4, false, false, staged<true, 2, 4, false>},
-    {4, 4, false, false, staged<true, 4, 4, false>},
-    {2, 2, false, false, staged<true, 2, 2, false>},
-    {2, 8, false, false, staged<true, 2, 8, false>},
-    {1, 4, false, false, staged<true, 1, 4, false>},
-    {2, 4, true, false, staged<true, 2, 4, true>},
-    {4, 4, true, false, staged<true, 4, 4, true>},
-    {2, 8, true, false, staged<true, 2, 8, true>},
-    {2, 2, true, false, staged<true, 2, 2, true>},
-    {2, 4, true, true, pipelined<2, 4, true>},
-    {2, 8, true, true, pipelined<2, 8, true>},
+    {2, 4, false, 1, staged<true, 2, 4, false>},
+    {4, 4, false, 1, staged<true, 4, 4, false>},
+    {2, 2, false, 1, staged<true, 2, 2, false>},
+    {2, 8, false, 1, staged<true, 2, 8, false>},
+    {1, 4, false, 1, staged<true, 1, 4, false>},
+    {2, 4, true, 1, staged<true, 2, 4, true>},
+    {4, 4, true, 1, staged<true, 4, 4, true>},
+    {2, 8, true, 1, staged<true, 2, 8, true>},
+    {2, 2, true, 1, staged<true, 2, 2, true>},
+    {2, 4, true, 2, pipelined<2, 4, true, false>},
+    {2, 8, true, 2, pipelined<2, 8, true, false>},
+    {2, 4, true, 3, pipelined<2, 4, true, true>},
 };
 
 bool column_variant_f32(const ColumnVariant &v) {
-    return find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.pipe) != nullptr;
+    return find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.sched) != nullptr;
 }
 
 hipError_t launch_column_f32(bool fused, const ColumnArgs &a, const ColumnVariant &v, hipStream_t st) {
     if (!fused) return staged<false, 2, 4, false>(a, st);
-    const ColumnEntry *e = find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.pipe);
+    const ColumnEntry *e = find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.sched);
     return e ? e->launch(a, st) : hipErrorInvalidValue;
 }
 

@@ -55,6 +55,10 @@ template <> struct Storage<uint16_t> {
     }
 };
 
+// Resident workgroups of a kernel with `block` threads on the current device
+// (host side; 0 if the runtime cannot say).
+int resident_workgroups(const void *kernel, int block);
+
 // ---------------------------------------------------------------------------
 // Workgroup -> tile map aware of the 8 XCDs of MI355X.  Consecutive
 // workgroup ids are dispatched round-robin over the XCDs, each of which has a

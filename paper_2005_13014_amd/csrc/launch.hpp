@@ -13,12 +13,15 @@ enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
 // Column kernels (column.hpp): register-resident half columns serve
 // nk <= KMAX_COLUMN.  A fused variant is chosen by rows per workgroup,
 // levels prefetched, non-temporal streams and the level-loop schedule
-// (staged, or pipelined so hdiff of one level overlaps the elimination of an
-// earlier one); only the compiled combinations are accepted.
+// (staged; pipelined, so hdiff of one level overlaps the elimination of an
+// earlier one; or pipelined on a persistent grid that chains tiles); only the
+// compiled combinations are accepted.
 constexpr int KMAX_COLUMN = 96;
+enum { SCHED_STAGED = 1, SCHED_PIPELINED = 2, SCHED_PERSISTENT = 3 };
 struct ColumnVariant {
     int tile_j, prefetch;
-    bool nt, pipe;
+    bool nt;
+    int sched;  // SCHED_*
 };
 bool column_variant_f64(const ColumnVariant &v);
 bool column_variant_f32(const ColumnVariant &v);
@@ -60,5 +63,6 @@ hipError_t launch_adjoint(int dtype, const AdjointArgs &a, void *scratch, hipStr
 
 // Streaming copy used as the bandwidth probe (probe.hip).
 hipError_t launch_probe_copy(const void *src, void *dst, long long nbytes, hipStream_t st);
+hipError_t launch_probe_read(const void *src, long long nbytes, unsigned key, void *sink, hipStream_t st);
 
 }  // namespace stl

@@ -1,23 +1,73 @@
-// Bandwidth probe: a plain streaming copy in 16-byte vectors, the ceiling the
-// memory-bound stencil kernels are measured against.
+// Bandwidth probes: the measured HBM ceilings the memory-bound stencil kernels
+// are compared with, and the calibration of the traffic counters.  Each lane
+// moves four 16-byte vectors per trip, all loads issued before any store, so
+// every wave keeps 4 KiB in flight.
 #include "launch.hpp"
 
 namespace stl {
 
-__global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
-                                                long long n) {
-    const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
-    for (long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; q < n; q += stride)
-        dst[q] = src[q];
+constexpr int PROBE_UNROLL = 4, PROBE_BLOCK = 256;
+
+__global__ __launch_bounds__(PROBE_BLOCK) void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                        long long n) {
+    const long long stride = static_cast<long long>(gridDim.x) * PROBE_BLOCK * PROBE_UNROLL;
+    for (long long base = static_cast<long long>(blockIdx.x) * PROBE_BLOCK * PROBE_UNROLL + threadIdx.x;
+         base < n; base += stride) {
+        uint4 v[PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) {
+            const long long q = base + static_cast<long long>(u) * PROBE_BLOCK;
+            if (q < n) v[u] = src[q];
+        }
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) {
+            const long long q = base + static_cast<long long>(u) * PROBE_BLOCK;
+            if (q < n) dst[q] = v[u];
+        }
+    }
+}
+
+// Reads n vectors; the XOR of everything read is stored only if it equals a
+// value the caller passes (so the loads cannot be dropped, and in practice
+// nothing is written).
+__global__ __launch_bounds__(PROBE_BLOCK) void k_read16(const uint4 *__restrict__ src, long long n,
+                                                        unsigned key, unsigned *__restrict__ sink) {
+    const long long stride = static_cast<long long>(gridDim.x) * PROBE_BLOCK * PROBE_UNROLL;
+    unsigned acc = 0;
+    for (long long base = static_cast<long long>(blockIdx.x) * PROBE_BLOCK * PROBE_UNROLL + threadIdx.x;
+         base < n; base += stride) {
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) {
+            const long long q = base + static_cast<long long>(u) * PROBE_BLOCK;
+            if (q < n) {
+                const uint4 v = src[q];
+                acc ^= v.x ^ v.y ^ v.z ^ v.w;
+            }
+        }
+    }
+    if (acc == key) sink[0] = acc;
+}
+
+static unsigned probe_blocks(long long n, long long cap) {
+    long long blocks = (n + PROBE_BLOCK * PROBE_UNROLL - 1) / (PROBE_BLOCK * PROBE_UNROLL);
+    return static_cast<unsigned>(blocks < cap ? blocks : cap);
 }
 
 hipError_t launch_probe_copy(const void *src, void *dst, long long nbytes, hipStream_t st) {
     const long long n = nbytes / 16;
     if (n == 0) return hipSuccess;
-    long long blocks = (n + 255) / 256;
-    if (blocks > 256 * 64) blocks = 256 * 64;  // 64 workgroups per CU, grid-stride beyond
-    hipLaunchKernelGGL(k_copy16, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+    // 64 workgroups per CU (the best measured grid), grid-stride beyond.
+    hipLaunchKernelGGL(k_copy16, dim3(probe_blocks(n, 256 * 64)), dim3(PROBE_BLOCK), 0, st,
                        static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_read(const void *src, long long nbytes, unsigned key, void *sink, hipStream_t st) {
+    const long long n = nbytes / 16;
+    if (n == 0) return hipSuccess;
+    // 8 workgroups per CU (the best measured grid for reads), grid-stride beyond.
+    hipLaunchKernelGGL(k_read16, dim3(probe_blocks(n, 256 * 8)), dim3(PROBE_BLOCK), 0, st,
+                       static_cast<const uint4 *>(src), n, key, static_cast<unsigned *>(sink));
     return hipGetLastError();
 }
 

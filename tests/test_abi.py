@@ -148,6 +148,12 @@ def test_scalar_and_config_checks():
     assert fused(spaced(7), dt=float("nan")) == 9
     assert vadv(spaced(6), dt=float("inf")) == 9
     assert fused(spaced(7), cfg=B.config(tile_j=3, prefetch=4)) == 7
+    assert fused(spaced(7), cfg=B.config(schedule=4)) == 9
+    assert fused(spaced(7), cfg=B.config(schedule=-1)) == 9
+    assert fused(spaced(7), cfg=B.config(nontemporal=2)) == 9
+    # a compiled tile shape with a schedule it is not compiled for
+    assert fused(spaced(7), cfg=B.config(tile_j=1, prefetch=4, nontemporal=1, schedule=2)) == 7
+    assert fused(spaced(7), cfg=B.config(tile_j=2, prefetch=8, nontemporal=1, schedule=3)) == 7
 
 
 def test_offsets_beyond_32_bits_are_unsupported():
@@ -167,6 +173,10 @@ def test_probe_copy_validation():
     assert lib.stencil_probe_copy(None, ctypes.c_void_p(FAKE), 16, None) == 1
     assert lib.stencil_probe_copy(ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE + 1024), 17, None) == 9
     assert lib.stencil_probe_copy(ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE + 16), 64, None) == 6
+    assert lib.stencil_probe_read(None, 16, 0, ctypes.c_void_p(FAKE), None) == 1
+    assert lib.stencil_probe_read(ctypes.c_void_p(FAKE), 16, 0, None, None) == 1
+    assert lib.stencil_probe_read(ctypes.c_void_p(FAKE), 24, 0, ctypes.c_void_p(FAKE), None) == 9
+    assert lib.stencil_probe_read(ctypes.c_void_p(FAKE + 8), 16, 0, ctypes.c_void_p(FAKE), None) == 9
 
 
 # ---- batched program validation --------------------------------------------

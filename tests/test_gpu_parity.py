@@ -143,7 +143,7 @@ def test_config3_full_size(dtype, n):
 
 @pytest.mark.parametrize("tj,pf,nt,sched", [(2, 4, -1, 1), (4, 4, -1, 1), (2, 2, -1, 1), (2, 8, -1, 1),
                                             (1, 4, -1, 1), (2, 4, 1, 1), (4, 4, 1, 1), (2, 8, 1, 1),
-                                            (2, 2, 1, 1), (2, 4, 1, 2), (2, 8, 1, 2)])
+                                            (2, 2, 1, 1), (2, 4, 1, 2), (2, 8, 1, 2), (2, 4, 1, 3)])
 def test_fused_variants_are_bitwise_identical(tj, pf, nt, sched):
     ni, nj, nk = 200, 37, 80
     f = inputs.fields(ni, nj, nk, 2, seed=SEED + 4, storage="f32")
@@ -161,11 +161,24 @@ def test_pipelined_schedule_every_depth(nk):
     ni, nj = 70, 5
     f = inputs.fields(ni, nj, nk, 2, seed=SEED + 40 + nk, storage="f32")
     staged = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(schedule=1)).to_numpy(interior=True)
-    for pf in (4, 8):
-        x = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(prefetch=pf, nontemporal=1, schedule=2))
-        assert np.array_equal(x.to_numpy(interior=True), staged), pf
+    for pf, sched in ((4, 2), (8, 2), (4, 3)):
+        x = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(prefetch=pf, nontemporal=1, schedule=sched))
+        assert np.array_equal(x.to_numpy(interior=True), staged), (pf, sched)
         assert halo_untouched(x)
     assert normwise(staged, ref_hdiff_vadv(f, 2)) <= TOL["f32"]
+
+
+@pytest.mark.parametrize("nk", [80, 37])
+def test_persistent_schedule_walks_several_tiles(nk):
+    """More tiles than resident workgroups (4 x 151 = 604 ragged tiles), so
+    workgroups of the persistent grid chain tiles: bitwise equal to the
+    one-shot staged grid, halos untouched."""
+    ni, nj = 200, 301
+    f = inputs.fields(ni, nj, nk, 2, seed=SEED + 60 + nk, storage="f32")
+    staged = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(schedule=1)).to_numpy(interior=True)
+    x = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(prefetch=4, nontemporal=1, schedule=3))
+    assert np.array_equal(x.to_numpy(interior=True), staged)
+    assert halo_untouched(x)
 
 
 def test_deterministic_and_wider_halo():
@@ -196,3 +209,22 @@ def test_probe_copy():
     B.stencil_probe_copy(src, dst, n * 4)
     torch.cuda.synchronize()
     assert torch.equal(src, dst)
+    # A ragged size (not a multiple of the 4 x 256 vectors a workgroup moves per trip).
+    m = 4 * (1000 * 4 + 3)
+    dst2 = torch.zeros(n, device="cuda")
+    B.stencil_probe_copy(src, dst2, m * 4)
+    torch.cuda.synchronize()
+    assert torch.equal(dst2[:m], src[:m]) and not dst2[m:].any()
+
+
+def test_probe_read():
+    n = 1 << 22
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    sink = torch.full((4,), 7, dtype=torch.int32, device="cuda")
+    # All-equal 16-byte vectors cancel pairwise: every lane's checksum is 0.
+    B.stencil_probe_read(src, n * 4, 1, sink)
+    torch.cuda.synchronize()
+    assert sink.tolist() == [7, 7, 7, 7]
+    B.stencil_probe_read(src, n * 4, 0, sink)
+    torch.cuda.synchronize()
+    assert sink[0].item() == 0 and sink[1:].tolist() == [7, 7, 7]
