@@ -21,9 +21,24 @@ static hipError_t staged(const ColumnArgs &a, hipStream_t st) {
                           : launch_column_t<double, FUSED, TJ, PF, 48, 1, NT>(a, st);
 }
 
+template <int TJ, int PF, bool NT, bool CHAIN>
+static hipError_t pipelined(const ColumnArgs &a, hipStream_t st) {
+    const int m = (a.K + 1) / 2;
+    if (m <= 16) return a.K == 32 ? launch_column_pipe_t<double, TJ, PF, 16, 2, NT, true, CHAIN>(a, st)
+                                  : launch_column_pipe_t<double, TJ, PF, 16, 2, NT, false, CHAIN>(a, st);
+    if (m <= 32) return a.K == 64 ? launch_column_pipe_t<double, TJ, PF, 32, 1, NT, true, CHAIN>(a, st)
+                                  : launch_column_pipe_t<double, TJ, PF, 32, 1, NT, false, CHAIN>(a, st);
+    if (m <= 40) return a.K == 80 ? launch_column_pipe_t<double, TJ, PF, 40, 1, NT, true, CHAIN>(a, st)
+                                  : launch_column_pipe_t<double, TJ, PF, 40, 1, NT, false, CHAIN>(a, st);
+    return a.K == 96 ? launch_column_pipe_t<double, TJ, PF, 48, 1, NT, true, CHAIN>(a, st)
+                     : launch_column_pipe_t<double, TJ, PF, 48, 1, NT, false, CHAIN>(a, st);
+}
+
 static const ColumnEntry kFused[] = {
     {2, 2, false, 1, staged<true, 2, 2, false>},
     {2, 4, false, 1, staged<true, 2, 4, false>},
+    {2, 2, true, 1, staged<true, 2, 2, true>},
+    {2, 2, true, 2, pipelined<2, 2, true, false>},
 };
 
 bool column_variant_f64(const ColumnVariant &v) {

@@ -153,6 +153,26 @@ def test_fused_variants_are_bitwise_identical(tj, pf, nt, sched):
     assert np.array_equal(got.to_numpy(interior=True), base)
 
 
+@pytest.mark.parametrize("dtype,tj,pf,nt", [("f64", 2, 2, 1), ("f64", 2, 2, -1), ("bf16", 2, 4, 1),
+                                             ("bf16", 2, 8, 1), ("bf16", 4, 4, -1)])
+@pytest.mark.parametrize("nk", [7, 80])
+def test_other_storage_variants_are_bitwise_identical(dtype, tj, pf, nt, nk):
+    """FP64 and bf16 storage: every compiled tile shape, prefetch depth,
+    cache policy and schedule gives the same bits as the staged default."""
+    ni, nj = 130, 9
+    f = inputs.fields(ni, nj, nk, 2, seed=SEED + 80 + nk, storage=dtype)
+    base = run_hdiff_vadv(f, ni, nj, nk, 2, dtype, cfg=B.config(schedule=1)).to_numpy(interior=True)
+    for sched in (1, 2):
+        cfg = B.config(tile_j=tj, prefetch=pf, nontemporal=nt, schedule=sched)
+        try:
+            x = run_hdiff_vadv(f, ni, nj, nk, 2, dtype, cfg=cfg)
+        except B.StencilError as e:
+            assert e.status == "E_UNSUPPORTED"  # this combination is not compiled
+            continue
+        assert np.array_equal(x.to_numpy(interior=True), base), sched
+        assert halo_untouched(x)
+
+
 @pytest.mark.parametrize("nk", [1, 2, 3, 4, 5, 9, 31, 32, 33, 64, 65, 79, 80, 81, 96])
 def test_pipelined_schedule_every_depth(nk):
     """The pipelined level loop has its own prologue and drain; every column
