@@ -154,14 +154,24 @@ int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field_t *coeff,
  *   gcoeff = -gh * (flx - flx(i-1) + fly - fly(j-1))
  *   gu = gh + masked transposed flux and Laplacian stencils applied to gh
  * Inputs: u (halo >= 2), coeff, wcon, a, b, c, w (interior read only).
+ *   ga(k) = -lam(k) x(k-1), gb(k) = -lam(k) x(k), gc(k) = -lam(k) x(k+1)
+ *                             (ga(0) = gc(K-1) = 0: those entries lie outside
+ *                             the matrix)
+ * Inputs: u (halo >= 2), coeff, wcon, a, b, c, w (interior read only); x,
+ * the forward result x = vadv(hdiff(u)) (interior read only), needed only
+ * for ga, gb, gc.
  * Outputs: gu (needs halo >= 2: its interior and 2-cell ring are
  * overwritten; the four 3-cell corner notches of the ring receive 0),
- * gcoeff and gwcon (interior).  Uses library-owned device scratch. */
+ * gcoeff and gwcon (interior); optionally ga, gb, gc (interior; NULL skips
+ * each, and x may be NULL when all three are NULL).  Uses library-owned
+ * device scratch. */
 int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stencil_field_t *coeff,
                                const stencil_field_t *wcon, const stencil_field_t *a,
                                const stencil_field_t *b, const stencil_field_t *c, double dt,
                                const stencil_field_t *w, const stencil_field_t *gu,
                                const stencil_field_t *gcoeff, const stencil_field_t *gwcon,
+                               const stencil_field_t *x, const stencil_field_t *ga,
+                               const stencil_field_t *gb, const stencil_field_t *gc,
                                const stencil_config_t *cfg, void *stream);
 
 /* ---- batched timestep program ------------------------------------------ */

@@ -6,7 +6,9 @@ field: the gradient of u covers the interior and the 2-cell ring that the
 13-point diamond reads, those of coeff and wcon the interior; every other
 element of a gradient buffer is zero.  The backward pass is the hand-written
 adjoint (``stencil_hdiff_vadv_adjoint``) with the limiter decisions of the
-forward pass held fixed.  No gradient flows to a, b, c or dt.
+forward pass held fixed; the gradients of the matrix a, b, c (interior; the
+entries a(0) and c(K-1) outside the matrix get 0) come from the same
+transposed solve and the saved forward result.  No gradient flows to dt.
 """
 from __future__ import annotations
 
@@ -33,7 +35,7 @@ class HdiffVadv(torch.autograd.Function):
                                                            c_buf))
         x = x_lay.like(fill=0.0)
         B.stencil_hdiff_vadv(u, coeff, wcon, a, b, c, dt, x)
-        ctx.save_for_backward(u_buf, coeff_buf, wcon_buf, a_buf, b_buf, c_buf)
+        ctx.save_for_backward(u_buf, coeff_buf, wcon_buf, a_buf, b_buf, c_buf, x.buf)
         ctx.meta = meta
         return x.buf
 
@@ -41,13 +43,17 @@ class HdiffVadv(torch.autograd.Function):
     def backward(ctx, gx_buf):
         lay, dt = ctx.meta
         x_lay = lay
-        u, coeff, wcon, a, b, c = (_wrap(t, lay) for t in ctx.saved_tensors)
+        u, coeff, wcon, a, b, c, x = (_wrap(t, lay) for t in ctx.saved_tensors)
         w = _wrap(gx_buf.contiguous(), x_lay)
         gu, gcoeff, gwcon = (lay.like(fill=0.0) for _ in range(3))
-        B.stencil_hdiff_vadv_adjoint(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon)
         need = ctx.needs_input_grad
+        gm = [lay.like(fill=0.0) if need[3 + q] else None for q in range(3)]
+        B.stencil_hdiff_vadv_adjoint(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon,
+                                     x=x if any(g is not None for g in gm) else None,
+                                     ga=gm[0], gb=gm[1], gc=gm[2])
         return (gu.buf if need[0] else None, gcoeff.buf if need[1] else None,
-                gwcon.buf if need[2] else None, None, None, None, None)
+                gwcon.buf if need[2] else None, *(g.buf if g is not None else None for g in gm),
+                None)
 
 
 def hdiff_vadv(u, coeff, wcon, a, b, c, dt):

@@ -73,8 +73,8 @@ _SIGNATURES = {
     "stencil_hdiff": [_P, _P, _P, _C, _V],
     "stencil_vadv": [_P, _P, _P, _P, _P, ctypes.c_double, _P, _C, _V],
     "stencil_hdiff_vadv": [_P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _C, _V],
-    "stencil_hdiff_vadv_adjoint": [_P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _C,
-                                   _V],
+    "stencil_hdiff_vadv_adjoint": [_P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P, _P,
+                                   _P, _P, _C, _V],
     "stencil_program_run": [ctypes.POINTER(Program), _V],
     "stencil_last_error": [],
     "stencil_abi_version": [],
@@ -229,11 +229,14 @@ def stencil_hdiff_vadv(u, coeff, wcon, a, b, c, dt, x, cfg=None, stream=None):
                                     _desc(c), float(dt), _desc(x), _cfg(cfg), _stream(stream)))
 
 
-def stencil_hdiff_vadv_adjoint(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon, cfg=None,
-                               stream=None):
+def stencil_hdiff_vadv_adjoint(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon, x=None, ga=None,
+                               gb=None, gc=None, cfg=None, stream=None):
+    """Reverse mode of x = vadv(hdiff(u)) for the loss sum(w * x): gu, gcoeff,
+    gwcon, and with the forward result x also any of ga, gb, gc."""
     _check(lib().stencil_hdiff_vadv_adjoint(
         _desc(u), _desc(coeff), _desc(wcon), _desc(a), _desc(b), _desc(c), float(dt), _desc(w),
-        _desc(gu), _desc(gcoeff), _desc(gwcon), _cfg(cfg), _stream(stream)))
+        _desc(gu), _desc(gcoeff), _desc(gwcon), _desc(x), _desc(ga), _desc(gb), _desc(gc), _cfg(cfg),
+        _stream(stream)))
 
 
 def stencil_program_run(prog, stream=None):

@@ -26,6 +26,8 @@ namespace stl {
 struct AdjArgs {
     const void *u, *coeff, *wcon, *a, *b, *c, *w;  // interior origins
     void *gu, *gcoeff, *gwcon;                      // interior origins (gu has a 2-cell halo)
+    const void *x;                                  // forward result (MATRIX only)
+    void *ga, *gb, *gc;                             // matrix gradients, each optional
     void *h, *gh;                                   // scratch, compute type, same strides
     int I, J, K, sj, sk;
     double dt;
@@ -35,7 +37,9 @@ struct AdjArgs {
 // Transposed Thomas solve and right-hand-side adjoint, one lane per column.
 // T^T has sub-diagonal c(k-1), diagonal b(k), super-diagonal a(k+1).
 // ---------------------------------------------------------------------------
-template <class T, int KMAX>
+// MATRIX: also ga(k) = -lam(k) x(k-1), gb(k) = -lam(k) x(k), gc(k) = -lam(k) x(k+1)
+// from the forward result x, for whichever of ga, gb, gc is set.
+template <class T, int KMAX, bool MATRIX>
 __global__ __launch_bounds__(256) void k_vadv_adjoint(AdjArgs p) {
     using S = Storage<T>;
     using C = typename S::C;
@@ -103,6 +107,13 @@ __global__ __launch_bounds__(256) void k_vadv_adjoint(AdjArgs p) {
         if (s < K) {
             const int o = col + s * sk;
             const double lam = (s == K - 1) ? D[s] : D[s] - P[s] * lam_up;
+            if constexpr (MATRIX) {
+                const T *__restrict__ fx = static_cast<const T *>(p.x);
+                const double xk = S::load(fx + o);
+                if (p.ga) S::store_d(static_cast<T *>(p.ga) + o, s > 0 ? -lam * S::load(fx + o - sk) : 0.0);
+                if (p.gb) S::store_d(static_cast<T *>(p.gb) + o, -lam * xk);
+                if (p.gc) S::store_d(static_cast<T *>(p.gc) + o, s < K - 1 ? -lam * S::load(fx + o + sk) : 0.0);
+            }
             const double hk = static_cast<double>(hs[o]), wk = static_cast<double>(S::load(wcon + o));
             if (s < K - 1) {
                 // Face s + 1/2, then level s + 1 is complete.
@@ -250,8 +261,11 @@ size_t adjoint_scratch_bytes(int dtype, int sk, int K) {
 
 template <class T, int KMAX>
 static void launch_vadv_adjoint_t(const AdjArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL((k_vadv_adjoint<T, KMAX>), dim3((a.I + 63) / 64, (a.J + 3) / 4), dim3(256), 0,
-                       st, a);
+    const dim3 grid((a.I + 63) / 64, (a.J + 3) / 4);
+    if (a.ga || a.gb || a.gc)
+        hipLaunchKernelGGL((k_vadv_adjoint<T, KMAX, true>), grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_vadv_adjoint<T, KMAX, false>), grid, dim3(256), 0, st, a);
 }
 
 template <class T>
@@ -283,6 +297,7 @@ hipError_t launch_adjoint(int dtype, const AdjointArgs &x, void *scratch, hipStr
     AdjArgs a{};
     a.u = x.u; a.coeff = x.coeff; a.wcon = x.wcon; a.a = x.a; a.b = x.b; a.c = x.c; a.w = x.w;
     a.gu = x.gu; a.gcoeff = x.gcoeff; a.gwcon = x.gwcon;
+    a.x = x.x; a.ga = x.ga; a.gb = x.gb; a.gc = x.gc;
     a.I = x.I; a.J = x.J; a.K = x.K; a.sj = x.sj; a.sk = x.sk;
     a.dt = x.dt;
     switch (dtype) {

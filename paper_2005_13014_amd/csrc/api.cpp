@@ -434,11 +434,27 @@ STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stenc
                                            const stencil_field_t *b, const stencil_field_t *c,
                                            double dt, const stencil_field_t *w,
                                            const stencil_field_t *gu, const stencil_field_t *gcoeff,
-                                           const stencil_field_t *gwcon, const stencil_config_t *cfg,
+                                           const stencil_field_t *gwcon, const stencil_field_t *xf,
+                                           const stencil_field_t *ga, const stencil_field_t *gb,
+                                           const stencil_field_t *gc, const stencil_config_t *cfg,
                                            void *stream) {
-    const stencil_field_t *fs[] = {u, coeff, wcon, a, b, c, w, gu, gcoeff, gwcon};
-    const char *names[] = {"u", "coeff", "wcon", "a", "b", "c", "w", "gu", "gcoeff", "gwcon"};
-    TRY(check_call(fs, names, 10, 3));
+    // Inputs first, outputs last (the alias check takes the last nout as outputs).
+    const stencil_field_t *fs[15];
+    const char *names[15];
+    int n = 0, nout = 0;
+    auto add = [&](const stencil_field_t *f, const char *name) { fs[n] = f; names[n++] = name; };
+    add(u, "u"); add(coeff, "coeff"); add(wcon, "wcon"); add(a, "a"); add(b, "b"); add(c, "c");
+    add(w, "w");
+    const bool matrix = ga || gb || gc;
+    if (matrix && !xf) return fail(STENCIL_E_NULL, "x (the forward result) is required for ga, gb, gc");
+    if (matrix) add(xf, "x");
+    const int nin = n;
+    add(gu, "gu"); add(gcoeff, "gcoeff"); add(gwcon, "gwcon");
+    if (ga) add(ga, "ga");
+    if (gb) add(gb, "gb");
+    if (gc) add(gc, "gc");
+    nout = n - nin;
+    TRY(check_call(fs, names, n, nout));
     TRY(check_halo(u, "u", 2));
     TRY(check_halo(gu, "gu", 2));
     TRY(check_dt(dt));
@@ -452,6 +468,10 @@ STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stenc
     x.u = u->origin; x.coeff = coeff->origin; x.wcon = wcon->origin;
     x.a = a->origin; x.b = b->origin; x.c = c->origin; x.w = w->origin;
     x.gu = gu->origin; x.gcoeff = gcoeff->origin; x.gwcon = gwcon->origin;
+    x.x = matrix ? xf->origin : nullptr;
+    x.ga = ga ? ga->origin : nullptr;
+    x.gb = gb ? gb->origin : nullptr;
+    x.gc = gc ? gc->origin : nullptr;
     x.I = u->ni; x.J = u->nj; x.K = u->nk;
     x.sj = static_cast<int>(u->sj); x.sk = static_cast<int>(u->sk);
     x.dt = dt;

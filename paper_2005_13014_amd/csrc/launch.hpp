@@ -54,6 +54,8 @@ hipError_t launch_plain(int dtype, const PlainArgs &a, hipStream_t st);
 struct AdjointArgs {
     const void *u, *coeff, *wcon, *a, *b, *c, *w;
     void *gu, *gcoeff, *gwcon;
+    const void *x;         // forward result; read only when ga, gb or gc is set
+    void *ga, *gb, *gc;    // optional matrix gradients (nullptr skips)
     int I, J, K, sj, sk;
     double dt;
 };

@@ -80,6 +80,31 @@ def vadv(fs, dt=10.0):
     return B.lib().stencil_vadv(*[r(f) for f in fs[:5]], dt, r(fs[5]), None, None)
 
 
+def adjoint(fs, x=None, ga=None, gb=None, gc=None, dt=10.0):
+    """fs: u, coeff, wcon, a, b, c, w, gu, gcoeff, gwcon."""
+    r = ctypes.byref
+    opt = lambda f: r(f) if f is not None else None  # noqa: E731
+    return B.lib().stencil_hdiff_vadv_adjoint(*[r(f) for f in fs[:6]], dt, *[r(f) for f in fs[6:10]],
+                                              opt(x), opt(ga), opt(gb), opt(gc), None, None)
+
+
+def test_adjoint_matrix_gradient_checks():
+    fs = spaced(14)
+    base, (x, ga, gb, gc) = fs[:10], fs[10:]
+    # the matrix gradients need the forward result
+    assert adjoint(base, ga=ga) == 1
+    assert "forward result" in B.stencil_last_error()
+    # an output overlapping an input, or another output
+    bad = fd(origin=fs[3].origin + 64)
+    assert adjoint(base, x=x, gb=bad) == 6
+    assert adjoint(base, x=x, ga=ga, gc=ga) == 6
+    # shape mismatch of an optional field
+    assert adjoint(base, x=fd(origin=x.origin, ni=15), gb=gb) == 3
+    # an empty interior is a no-op that still validates every field
+    empty = spaced(14, nk=0)
+    assert adjoint(empty[:10], x=empty[10], ga=empty[11], gb=empty[12], gc=empty[13]) == 0
+
+
 def test_null_descriptor_and_origin():
     u, c, o = spaced(3)
     assert hdiff(None, c, o) == 1

@@ -91,6 +91,56 @@ def test_adjoint_config5_256x256x80(dtype):
     check(gpu_adjoint(g, dtype), oracle_adjoint(f, masks), TOL[dtype], "C5 adjoint %s" % dtype)
 
 
+def gpu_matrix_adjoint(g, dtype, x, fill=-7.0):
+    out = {n: g["u"].like(fill=fill) for n in ("gu", "gcoeff", "gwcon", "ga", "gb", "gc")}
+    B.stencil_hdiff_vadv_adjoint(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT, g["w"],
+                                 out["gu"], out["gcoeff"], out["gwcon"], x=x, ga=out["ga"],
+                                 gb=out["gb"], gc=out["gc"])
+    torch.cuda.synchronize()
+    return out
+
+
+def gpu_forward(g):
+    x = g["u"].like(fill=0.0)
+    B.stencil_hdiff_vadv(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT, x)
+    torch.cuda.synchronize()
+    return x
+
+
+@pytest.mark.parametrize("dtype,shape", [("f64", (64, 64, 60)), ("f64", (70, 13, 5)), ("f64", (3, 2, 1)),
+                                         ("f64", (131, 9, 96)), ("f32", (99, 17, 33)),
+                                         ("f32", (256, 256, 80))])
+def test_matrix_gradients_match_oracle(dtype, shape):
+    """ga, gb, gc from the transposed solve and the forward result, against
+    the oracle's (FP32: under the FP32 limiter decisions); the other three
+    gradients are unchanged by asking for them."""
+    ni, nj, nk = shape
+    f, g = setup(ni, nj, nk, dtype, SEED + 55)
+    masks = None if dtype == "f64" else limiter_masks(f["u"], 2, dtype)
+    kx, ky = masks if masks is not None else (None, None)
+    ref = oracle.hdiff_vadv_adjoint(f["u"], 2, f["coeff"], 2, f["wcon"], 2, f["a"], 2, f["b"], 2,
+                                    f["c"], 2, DT, interior(f["w"], 2), 0, matrix=True, force_kx=kx,
+                                    force_ky=ky)
+    out = gpu_matrix_adjoint(g, dtype, gpu_forward(g))
+    errs = [normwise(out[n].to_numpy(interior=True), r) for n, r in zip(("ga", "gb", "gc"), ref[3:])]
+    note("matrix gradients %s %s normwise ga %.2e gb %.2e gc %.2e" % (dtype, shape, *errs))
+    assert max(errs) <= TOL[dtype], errs
+    assert np.all(out["ga"].to_numpy(interior=True)[0] == 0)
+    assert np.all(out["gc"].to_numpy(interior=True)[-1] == 0)
+    plain = gpu_adjoint(g, dtype)
+    for n in ("gu", "gcoeff", "gwcon"):
+        got = out[n].to_numpy()
+        if n != "gu":
+            got = out[n].to_numpy(interior=True)
+            assert np.array_equal(got, plain[n].to_numpy(interior=True))
+        else:
+            assert np.array_equal(got, plain[n].to_numpy())
+    # matrix gradients write their interior only
+    for n in ("ga", "gb", "gc"):
+        full = out[n].to_numpy()
+        assert np.all(full[:, :2] == -7.0) and np.all(full[:, :, :2] == -7.0)
+
+
 def test_adjoint_against_central_differences():
     # FP64 forward on the GPU, eps = 1e-6: L is piecewise linear in u and
     # linear in coeff and wcon, so central differences are exact up to
@@ -99,9 +149,8 @@ def test_adjoint_against_central_differences():
     # the few columns a probe touches differ).
     ni, nj, nk = 96, 40, 80
     f, g = setup(ni, nj, nk, "f64", SEED + 52)
-    out = gpu_adjoint(g, "f64")
-    grads = {"u": out["gu"].to_numpy(), "coeff": out["gcoeff"].to_numpy(),
-             "wcon": out["gwcon"].to_numpy()}
+    out = gpu_matrix_adjoint(g, "f64", gpu_forward(g))
+    grads = {n: out["g" + n].to_numpy() for n in ("u", "coeff", "wcon", "a", "b", "c")}
     wl = interior(f["w"], 2)
     kx0, ky0 = limiter_masks(f["u"], 2, "f64")
     rng = np.random.default_rng(7)
@@ -121,9 +170,11 @@ def test_adjoint_against_central_differences():
             vals.append(x.to_numpy(interior=True))
         return float((wl * (vals[0] - vals[1])).sum())
 
-    for name in ("u", "coeff", "wcon"):
+    for name in ("u", "coeff", "wcon", "a", "b", "c"):
         for _ in range(8):
             k = int(rng.integers(0, nk))
+            if name == "a" and k == 0 or name == "c" and k == nk - 1:
+                continue  # outside the matrix
             lo = -2 if name == "u" else 0
             j = int(rng.integers(lo, nj - lo))
             i = int(rng.integers(lo, ni - lo))
@@ -139,7 +190,7 @@ def test_adjoint_against_central_differences():
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (name, k, j, i, fd, an)
             checked += 1
     note("central differences: %d probes agree" % checked)
-    assert checked >= 18
+    assert checked >= 36
 
 
 def test_autograd_function_matches_adjoint():
@@ -148,16 +199,23 @@ def test_autograd_function_matches_adjoint():
     u = B.Field.from_numpy(f["u"], 2, "f64")
     coeff = B.Field.from_numpy(f["coeff"], 2, "f64")
     wcon = B.Field.from_numpy(f["wcon"], 2, "f64")
-    for fld in (u, coeff, wcon):
+    a = B.Field.from_numpy(f["a"], 2, "f64")
+    c = B.Field.from_numpy(f["c"], 2, "f64")
+    for fld in (u, coeff, wcon, a, c):
         fld.buf.requires_grad_(True)
-    x = AG.hdiff_vadv(u, coeff, wcon, g["a"], g["b"], g["c"], DT)
+    x = AG.hdiff_vadv(u, coeff, wcon, a, g["b"], c, DT)
     wbuf = g["w"].buf.detach()
     loss = (x.buf * wbuf).sum()
     loss.backward()
-    ref = gpu_adjoint(g, "f64")
+    ref = gpu_matrix_adjoint(g, "f64", gpu_forward(g), fill=0.0)
     assert torch.equal(u.buf.grad, ref["gu"].buf)
     assert torch.equal(coeff.buf.grad, ref["gcoeff"].buf)
     assert torch.equal(wcon.buf.grad, ref["gwcon"].buf)
+    # a and c carry gradients on the interior only (the rest of the buffer is 0)
+    for fld, n in ((a, "ga"), (c, "gc")):
+        got = B.Field(fld.buf.grad, fld.origin, ni, nj, nk, 2, 2, fld.sj, fld.sk, "f64")
+        assert np.array_equal(got.to_numpy(interior=True), ref[n].to_numpy(interior=True))
+    assert g["b"].buf.grad is None
 
 
 def test_torch_gradcheck_small():
