@@ -374,6 +374,8 @@ def main():
                     help="only the headline measurement (no variants, no CPU baseline)")
     ap.add_argument("--with-copy", action="store_true",
                     help="with --quick: also run the copy probe (counter calibration)")
+    ap.add_argument("--only", choices=["timestep", "adjoint"],
+                    help="run only this variant and print its figures (for profiling)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write the profile summaries under profiles/ from rocprofv3 output in DIR "
                          "(no GPU needed)")
@@ -391,6 +393,10 @@ def main():
     torch.cuda.init()
     dev = torch.cuda.get_device_properties(0)
     log("device:", dev.name, "CUs:", dev.multi_processor_count)
+    if args.only:
+        fn = {"timestep": variant_program, "adjoint": variant_adjoint}[args.only]
+        print(json.dumps({"variant": args.only, "result": fn()}), flush=True)
+        return
 
     ni, nj, nk = args.size
     dtype = args.dtype

@@ -34,121 +34,217 @@ struct AdjArgs {
 };
 
 // ---------------------------------------------------------------------------
-// Transposed Thomas solve and right-hand-side adjoint, one lane per column.
-// T^T has sub-diagonal c(k-1), diagonal b(k), super-diagonal a(k+1).
+// Transposed Thomas solve and right-hand-side adjoint.  T^T has, in row k,
+// c(k-1) below the diagonal, b(k) on it and a(k+1) above it.  Like the
+// forward column kernel, two lanes share a column: half 0 eliminates rows
+// [0, M) upward and half 1 rows [M, K) downward (M = ceil(K/2)), the two
+// interface rows are solved as a 2 x 2 system, and each half walks back
+// outward from the interface.  During that walk a level is finished as soon
+// as lam is known on both of its sides:
+//   Fhat(k+1/2) = -dt (lam(k) - lam(k+1))
+//   gh(k)    = lam(k) + sum over its faces f of Fhat(f) wbar(f) / 2
+//   gwcon(k) = sum over its faces f of Fhat(f) hbar(f) / 2
+// and with MATRIX also ga(k) = -lam(k) x(k-1), gb(k) = -lam(k) x(k),
+// gc(k) = -lam(k) x(k+1).  A half with fewer than KH levels starts with
+// identity padding rows so the elimination loop has no run-time guards.
 // ---------------------------------------------------------------------------
-// MATRIX: also ga(k) = -lam(k) x(k-1), gb(k) = -lam(k) x(k), gc(k) = -lam(k) x(k+1)
-// from the forward result x, for whichever of ga, gb, gc is set.
-template <class T, int KMAX, bool MATRIX>
-__global__ __launch_bounds__(256) void k_vadv_adjoint(AdjArgs p) {
+template <class T, int TJ, int PF, int KH, bool MATRIX>
+__global__ __launch_bounds__(128 * TJ) __attribute__((amdgpu_waves_per_eu(2, 8))) void
+k_vadv_adjoint(AdjArgs p, int nbi) {
+#pragma clang fp contract(off)
     using S = Storage<T>;
     using C = typename S::C;
-    const T *__restrict__ fa = static_cast<const T *>(p.a);
-    const T *__restrict__ fb = static_cast<const T *>(p.b);
-    const T *__restrict__ fc = static_cast<const T *>(p.c);
-    const T *__restrict__ fw = static_cast<const T *>(p.w);
-    const T *__restrict__ wcon = static_cast<const T *>(p.wcon);
-    const C *__restrict__ hs = static_cast<const C *>(p.h);
-    C *__restrict__ ghs = static_cast<C *>(p.gh);
-    T *__restrict__ gwc = static_cast<T *>(p.gwcon);
+    using IO = BufIO<T>;
+    using IOC = BufIO<C>;
+    constexpr int NH = 64 * TJ;
+    constexpr uint32_t ES = sizeof(T), EC = sizeof(C);
+    __shared__ double2 xch[2 * NH];
 
-    const int gi = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int gj = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (gi >= p.I || gj >= p.J) return;
-    const int col = gi + gj * p.sj, sk = p.sk, K = p.K;
-    const double dt = p.dt;
+    const int tid = threadIdx.x;
+    const int half = __builtin_amdgcn_readfirstlane(tid >= NH ? 1 : 0);
+    const int l = tid - half * NH, ti = l & 63;
+    const int tj = __builtin_amdgcn_readfirstlane(l >> 6);
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int gi = (tile % nbi) * 64 + ti, gj = (tile / nbi) * TJ + tj;
+    const int I = p.I, J = p.J, K = p.K;
+    const bool active = gi < I && gj < J;
+    // Lanes past a ragged edge work on a valid column and store nothing.
+    const uint32_t col = static_cast<uint32_t>(min(gi, I - 1) + min(gj, J - 1) * p.sj);
+    const uint32_t vt = col * ES, vc = col * EC;
+    const uint32_t skt = static_cast<uint32_t>(p.sk) * ES, skc = static_cast<uint32_t>(p.sk) * EC;
+    // Addressable bytes from an interior origin (the host checks < 2^31).
+    const uint32_t tbytes = static_cast<uint32_t>((static_cast<size_t>(I - 1) +
+                                                   static_cast<size_t>(J - 1) * p.sj +
+                                                   static_cast<size_t>(K - 1) * p.sk + 1) * ES);
+    const uint32_t cbytes = tbytes / ES * EC;
+    // The neighbour toward the far end multiplies "lower", the one toward the
+    // interface "upper": c(k-1) and a(k+1) in half 0, a(k+1) and c(k-1) in half 1.
+    const auto rlo = make_rsrc(half ? p.a : p.c, tbytes);
+    const auto rup = make_rsrc(half ? p.c : p.a, tbytes);
+    const auto rb = make_rsrc(p.b, tbytes);
+    const auto rw = make_rsrc(p.w, tbytes);
+    const auto rwc = make_rsrc(p.wcon, tbytes);
+    const auto rh = make_rsrc(p.h, cbytes);
+    const auto rgh = make_rsrc(p.gh, cbytes);
+    const auto rgw = make_rsrc(p.gwcon, tbytes);
 
-    // Forward elimination of T^T lam = w.  Row t is eliminated at step t + 1,
-    // once its super-diagonal a(t + 1) has been read.
-    double P[KMAX], D[KMAX];
-    double b_t = 0.0, w_t = 0.0, c_tm1 = 0.0, c_t = 0.0;
+    const int M = (K + 1) >> 1;
+    const int nsteps = half ? K - M : M;
+    const int shift = KH - nsteps;
+    auto level = [&](int t) { return half ? K - 1 - t : t; };
+    // Level of local index t clamped into the column (for loads whose value
+    // is unused outside it).
+    auto clampk = [&](int t) {
+        const int k = level(t);
+        return static_cast<uint32_t>(min(max(k, 0), K - 1));
+    };
+
+    // Elimination: ring of the next PF steps' b, w, lower (of level t, used at
+    // step t + 1) and upper (of level t + 1).
+    double rbv[PF], rwv[PF], rlov[PF], rupv[PF];
+    auto load = [&](int q, int s) {
+        const int t = max(s - shift, 0);
+        const uint32_t o = clampk(t) * skt, o1 = clampk(t + 1) * skt;
+        rbv[q] = IO::template load<2>(rb, vt, o);
+        rwv[q] = IO::template load<2>(rw, vt, o);
+        rlov[q] = IO::template load<2>(rlo, vt, o);
+        rupv[q] = IO::template load<2>(rup, vt, o1);
+    };
 #pragma unroll
-    for (int s = 0; s < KMAX; ++s) {
-        if (s < K) {
-            const int o = col + s * sk;
-            const double as = S::load(fa + o), bs = S::load(fb + o), cs = S::load(fc + o),
-                         ws = S::load(fw + o);
-            if (s > 0) {
-                const int t = s - 1;
-                if (t == 0) {
-                    const double r = recip(b_t);
-                    P[0] = as * r;
-                    D[0] = w_t * r;
-                } else {
-                    const int tm = t > 0 ? t - 1 : 0;
-                    const double r = recip(b_t - c_tm1 * P[tm]);
-                    P[t] = as * r;
-                    D[t] = (w_t - c_tm1 * D[tm]) * r;
-                }
-            }
-            c_tm1 = c_t;
-            c_t = cs;
-            b_t = bs;
-            w_t = ws;
-            if (s == K - 1) {
-                // Last row: no super-diagonal.
-                if (s == 0) {
-                    D[0] = w_t / b_t;
-                } else {
-                    const int tm = s > 0 ? s - 1 : 0;
-                    D[s] = (w_t - c_tm1 * D[tm]) / (b_t - c_tm1 * P[tm]);
-                }
-            }
+    for (int q = 0; q < PF && q < KH; ++q) load(q, q);
+
+    double P[KH], D[KH];
+    double lo_carry = 0.0;  // lower of this step's row: the far-side neighbour's coefficient
+#pragma unroll
+    for (int s = 0; s < KH; ++s) {
+        const int q = s % PF;
+        const bool pad = s < shift, first = s == shift;
+        double bt = rbv[q], wt = rwv[q], upt = rupv[q];
+        const double lot = first ? 0.0 : lo_carry;  // the far-end row has no lower neighbour
+        lo_carry = rlov[q];
+        if (s + PF < KH) load(q, s + PF);
+        // The interface row's upper belongs to the other half's first level;
+        // with an empty other half (K = 1) it is never used.
+        if (pad) {
+            bt = 1.0;
+            wt = 0.0;
+            upt = 0.0;
         }
+        if (s == 0) {
+            const double r = recip(bt);
+            P[0] = upt * r;
+            D[0] = wt * r;
+        } else {
+            const int sm = s > 0 ? s - 1 : 0;
+            const double r = recip(fmadd(-lot, P[sm], bt));
+            P[s] = upt * r;
+            D[s] = fmadd(-lot, D[sm], wt) * r;
+        }
+        pin(P[s]);
+        pin(D[s]);
     }
 
-    // Back-substitution lam(k) = D(k) - P(k) lam(k+1), walking down; level
-    // k + 1 is finished once lam(k) gives the face below it.
-    double lam_up = 0.0, fh_up = 0.0;   // lam(k+1), Fhat(k+3/2)
-    double h_up = 0.0, wc_up = 0.0;     // h(k+1), wcon(k+1)
-    double h_up2 = 0.0, wc_up2 = 0.0;   // h(k+2), wcon(k+2)
+    // Interface: x(M-1) + P0 x(M) = D0 and x(M) + P1 x(M-1) = D1 (lam here).
+    const double Pm = nsteps > 0 ? P[KH - 1] : 0.0, Dm = nsteps > 0 ? D[KH - 1] : 0.0;
+    xch[tid] = make_double2(Pm, Dm);
+    __syncthreads();
+    const double2 o2 = xch[half ? l : NH + l];
+    const double P0 = half ? o2.x : Pm, D0 = half ? o2.y : Dm;
+    const double P1 = half ? Pm : o2.x, D1 = half ? Dm : o2.y;
+    const double x_lo = fmadd(-P0, D1, D0) / fmadd(-P0, P1, 1.0);
+    const double x_hi = fmadd(-P1, x_lo, D1);
+    if (nsteps == 0) return;  // after the only barrier
+
+    // Outward walk.  "in" is the side toward the interface (local t + 1),
+    // "out" the side toward the far end.  dts orients the face flux: in half 0
+    // local t + 1 is the level above, in half 1 the level below.
+    const double dt = p.dt, dts = half ? -dt : dt;
+    const bool other = K - M > 0;  // the interface level has a neighbour across it
+    const auto rx = make_rsrc(MATRIX ? p.x : p.w, tbytes);
+    // wcon, h (and x) of local level t: a ring of the next WR levels out.
+    constexpr int WR = 4;
+    double rwc_[WR], rh_[WR], rx_[WR];
+    auto wload = [&](int q, int t) {
+        const uint32_t k = clampk(t);
+        rwc_[q] = IO::template load<2>(rwc, vt, k * skt);
+        rh_[q] = IOC::load(rh, vc, k * skc);
+        rx_[q] = MATRIX ? static_cast<double>(IO::template load<2>(rx, vt, k * skt)) : 0.0;
+    };
+    // Slot q holds local level (step index q) - shift, step index = static.
+    // Walk order: the interface level (step KH - 1), then steps KH - 2, ...
 #pragma unroll
-    for (int s = KMAX - 1; s >= 0; --s) {
-        if (s < K) {
-            const int o = col + s * sk;
-            const double lam = (s == K - 1) ? D[s] : D[s] - P[s] * lam_up;
-            if constexpr (MATRIX) {
-                const T *__restrict__ fx = static_cast<const T *>(p.x);
-                const double xk = S::load(fx + o);
-                if (p.ga) S::store_d(static_cast<T *>(p.ga) + o, s > 0 ? -lam * S::load(fx + o - sk) : 0.0);
-                if (p.gb) S::store_d(static_cast<T *>(p.gb) + o, -lam * xk);
-                if (p.gc) S::store_d(static_cast<T *>(p.gc) + o, s < K - 1 ? -lam * S::load(fx + o + sk) : 0.0);
-            }
-            const double hk = static_cast<double>(hs[o]), wk = static_cast<double>(S::load(wcon + o));
-            if (s < K - 1) {
-                // Face s + 1/2, then level s + 1 is complete.
-                const double fh = -dt * (lam - lam_up);
-                const double wbar = 0.5 * (wk + wc_up), hbar = 0.5 * (hk + h_up);
-                double g = lam_up, gw = 0.0;
-                g += 0.5 * fh * wbar;
-                gw += 0.5 * fh * hbar;
-                if (s + 1 < K - 1) {
-                    const double wbar2 = 0.5 * (wc_up + wc_up2), hbar2 = 0.5 * (h_up + h_up2);
-                    g += 0.5 * fh_up * wbar2;
-                    gw += 0.5 * fh_up * hbar2;
-                }
-                const int o1 = o + sk;
-                ghs[o1] = static_cast<C>(g);
-                S::store_d(gwc + o1, gw);
-                fh_up = fh;
-            }
-            h_up2 = h_up;
-            wc_up2 = wc_up;
-            h_up = hk;
-            wc_up = wk;
-            lam_up = lam;
-        }
+    for (int q = 0; q < WR; ++q) wload(q, KH - 1 - q - shift);
+    // The level across the interface.
+    double lam_in = half ? x_lo : x_hi;
+    double wc_in = 0.0, h_in = 0.0, x_in = 0.0;
+    if (other) {
+        const uint32_t k = clampk(nsteps);
+        wc_in = IO::template load<2>(rwc, vt, k * skt);
+        h_in = IOC::load(rh, vc, k * skc);
+        if constexpr (MATRIX) x_in = IO::template load<2>(rx, vt, k * skt);
     }
-    // Level 0: only the face above it.
-    {
-        double g = lam_up, gw = 0.0;
-        if (K > 1) {
-            const double wbar = 0.5 * (wc_up + wc_up2), hbar = 0.5 * (h_up + h_up2);
-            g += 0.5 * fh_up * wbar;
-            gw += 0.5 * fh_up * hbar;
+    bool has_in = other;
+    double lam = half ? x_hi : x_lo;  // lam of the current level
+    double wc_t = rwc_[0], h_t = rh_[0], x_t = rx_[0];
+    if (KH - 1 - WR >= 0) wload(0, KH - 1 - WR - shift);
+    double fh_in = 0.0, wb_in = 0.0, hb_in = 0.0;  // face between the current level and "in"
+    if (has_in) {
+        fh_in = -dts * (lam - lam_in);
+        wb_in = 0.5 * (wc_t + wc_in);
+        hb_in = 0.5 * (h_t + h_in);
+    }
+#pragma unroll
+    for (int st = KH - 1; st >= 0; --st) {
+        // Step index st is the current level (local st - shift); st - 1 the next one out.
+        if (st >= shift) {
+            const int t = st - shift;
+            const bool has_out = t > 0;
+            const int so = st > 0 ? st - 1 : 0;
+            const int q = (KH - 1 - so) % WR;
+            const double lam_o = has_out ? fmadd(-P[so], lam, D[so]) : 0.0;
+            const double wc_o = rwc_[q], h_o = rh_[q], x_o = rx_[q];
+            double g = lam, gw = 0.0, fh_o = 0.0, wb_o = 0.0, hb_o = 0.0;
+            if (has_in) {
+                g = fmadd(0.5 * fh_in, wb_in, g);
+                gw = fmadd(0.5 * fh_in, hb_in, gw);
+            }
+            if (has_out) {
+                fh_o = -dts * (lam_o - lam);
+                wb_o = 0.5 * (wc_t + wc_o);
+                hb_o = 0.5 * (h_t + h_o);
+                g = fmadd(0.5 * fh_o, wb_o, g);
+                gw = fmadd(0.5 * fh_o, hb_o, gw);
+            }
+            if (active) {
+                const uint32_t k = static_cast<uint32_t>(level(t));
+                IOC::store_d(rgh, vc, k * skc, g);
+                IO::template store_d<2>(rgw, vt, k * skt, gw);
+                if constexpr (MATRIX) {
+                    // x(k-1) and x(k+1): the far-end and interface sides, swapped in half 1.
+                    const double x_dn = half ? x_in : x_o, x_upv = half ? x_o : x_in;
+                    const bool has_dn = half ? has_in : has_out, has_up = half ? has_out : has_in;
+                    if (p.ga)
+                        IO::template store_d<2>(make_rsrc(p.ga, tbytes), vt, k * skt, has_dn ? -lam * x_dn : 0.0);
+                    if (p.gb) IO::template store_d<2>(make_rsrc(p.gb, tbytes), vt, k * skt, -lam * x_t);
+                    if (p.gc)
+                        IO::template store_d<2>(make_rsrc(p.gc, tbytes), vt, k * skt, has_up ? -lam * x_upv : 0.0);
+                }
+            }
+            // Step out: the face just used becomes the next level's "in" face.
+            fh_in = fh_o;
+            wb_in = wb_o;
+            hb_in = hb_o;
+            has_in = true;
+            lam_in = lam;
+            x_in = x_t;
+            lam = lam_o;
+            wc_t = wc_o;
+            h_t = h_o;
+            x_t = x_o;
         }
-        ghs[col] = static_cast<C>(g);
-        S::store_d(gwc + col, gw);
+        // Refill the slot just consumed with the level WR steps further out.
+        const int so = st > 0 ? st - 1 : 0;
+        if (st > 0 && so - WR >= 0) wload((KH - 1 - so) % WR, so - WR - shift);
     }
 }
 
@@ -259,13 +355,16 @@ size_t adjoint_scratch_bytes(int dtype, int sk, int K) {
     return 2 * (static_cast<size_t>(sk) * K * cs + 256);
 }
 
-template <class T, int KMAX>
+template <class T, int KH, int WPE_UNUSED = 2>
 static void launch_vadv_adjoint_t(const AdjArgs &a, hipStream_t st) {
-    const dim3 grid((a.I + 63) / 64, (a.J + 3) / 4);
+    constexpr int TJ = 2, PF = 4;
+    const int nbi = (a.I + 63) / 64, nbj = (a.J + TJ - 1) / TJ;
     if (a.ga || a.gb || a.gc)
-        hipLaunchKernelGGL((k_vadv_adjoint<T, KMAX, true>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_vadv_adjoint<T, TJ, PF, KH, true>), dim3(nbi * nbj), dim3(128 * TJ), 0, st, a,
+                           nbi);
     else
-        hipLaunchKernelGGL((k_vadv_adjoint<T, KMAX, false>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_vadv_adjoint<T, TJ, PF, KH, false>), dim3(nbi * nbj), dim3(128 * TJ), 0, st, a,
+                           nbi);
 }
 
 template <class T>
@@ -283,9 +382,11 @@ static hipError_t adjoint_run(AdjArgs a, void *scratch, hipStream_t st) {
                                         : std::is_same<T, float>::value ? DT_F32 : DT_BF16,
                                         hd, st);
     if (e != hipSuccess) return e;
-    if (a.K <= 32) launch_vadv_adjoint_t<T, 32>(a, st);
-    else if (a.K <= 64) launch_vadv_adjoint_t<T, 64>(a, st);
-    else launch_vadv_adjoint_t<T, 96>(a, st);
+    const int m = (a.K + 1) / 2;  // levels of the longer half
+    if (m <= 16) launch_vadv_adjoint_t<T, 16>(a, st);
+    else if (m <= 32) launch_vadv_adjoint_t<T, 32>(a, st);
+    else if (m <= 40) launch_vadv_adjoint_t<T, 40>(a, st);
+    else launch_vadv_adjoint_t<T, 48>(a, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nbi = (a.I + 4 + 63) / 64, nbj = (a.J + 4 + 3) / 4;

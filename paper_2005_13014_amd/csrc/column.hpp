@@ -111,16 +111,20 @@ __device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
 // level by level during the back-substitution.
 // NT: the read-once column inputs and the output use non-temporal accesses
 // (u is re-read by neighbouring tiles through L2 and keeps the default).
+// NTX: only the output is non-temporal (for column inputs that other
+// workgroups re-read, such as coefficients shared by several fields).
 // EXACT: nk == 2 KH, so both halves take exactly KH levels; every level
 // guard is then a compile-time constant and each barrier interval of the
 // level loop is one straight-line scheduling region.
-template <class T, bool FUSED, bool VDIFF, int TJ, int PF, int KH, bool NT = false, bool EXACT = false>
+template <class T, bool FUSED, bool VDIFF, int TJ, int PF, int KH, bool NT = false, bool EXACT = false,
+          bool NTX = NT>
 __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj, double kappa) {
 #pragma clang fp contract(off)
     using S = Storage<T>;
     using C = typename S::C;
     using IO = BufIO<T>;
-    constexpr int CP = NT ? 2 : 0;
+    constexpr int CP = NT ? 2 : 0;    // column inputs
+    constexpr int CPX = NTX ? 2 : 0;  // output
     constexpr int TI = 64, PI = TI + 4, PJ = TJ + 4, MR = PJ / TJ, NH = 64 * TJ;
     static_assert(PJ % TJ == 0, "tile rows must split evenly over the lanes");
     constexpr int TILE = PJ * PI + 64;  // + one dummy slot per lane of the side-loading wave
@@ -297,13 +301,13 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     double xn = half ? x_hi : x_lo;
     if constexpr (!VDIFF) {
         if (active && nsteps > 0)
-            IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, xn);
+            IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, xn);
 #pragma unroll
         for (int tt = KH - 2; tt >= 0; --tt) {
             if (tt >= shift) {
                 xn = fmadd(-P[tt], xn, D[tt]);
                 if (active)
-                    IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(tt - shift)) * sk_bytes, xn);
+                    IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(tt - shift)) * sk_bytes, xn);
             }
         }
     } else {
@@ -320,7 +324,7 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
             const double g_up = has_up ? up - x_cur : 0.0;
             const double g_dn = has_dn ? x_cur - dn : 0.0;
             const double y = fmadd(kappa, g_up - g_dn, x_cur);
-            if (active) IO::template store_d<CP>(rx, vcol, static_cast<uint32_t>(level(t_loc)) * sk_bytes, y);
+            if (active) IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(t_loc)) * sk_bytes, y);
         };
 #pragma unroll
         for (int tt = KH - 2; tt >= 0; --tt) {
@@ -618,7 +622,9 @@ k_column_batch(ColumnBatch b) {
     ColumnArgs a = sb.a;
     a.u = sb.u[f];
     a.x = sb.x[f];
-    column_tile<T, true, VDIFF, TJ, PF, KH>(a, tile % a.nbi, tile / a.nbi, b.kappa);
+    // Coefficients are shared by the fields of a subdomain (re-read through
+    // L2): default policy; the output streams.
+    column_tile<T, true, VDIFF, TJ, PF, KH, false, false, true>(a, tile % a.nbi, tile / a.nbi, b.kappa);
 }
 
 // ---------------------------------------------------------------------------
