@@ -47,6 +47,9 @@ static const ColumnEntry kFused[] = {
     {2, 4, true, 2, pipelined<2, 4, true, false>},
     {2, 8, true, 2, pipelined<2, 8, true, false>},
     {2, 4, true, 3, pipelined<2, 4, true, true>},
+    {4, 4, true, 2, pipelined<4, 4, true, false>},
+    {1, 4, true, 2, pipelined<1, 4, true, false>},
+    {2, 2, true, 2, pipelined<2, 2, true, false>},
 };
 
 bool column_variant_f32(const ColumnVariant &v) {

@@ -177,7 +177,7 @@ def test_scalar_and_config_checks():
     assert fused(spaced(7), cfg=B.config(schedule=-1)) == 9
     assert fused(spaced(7), cfg=B.config(nontemporal=2)) == 9
     # a compiled tile shape with a schedule it is not compiled for
-    assert fused(spaced(7), cfg=B.config(tile_j=1, prefetch=4, nontemporal=1, schedule=2)) == 7
+    assert fused(spaced(7), cfg=B.config(tile_j=1, prefetch=8, nontemporal=1, schedule=2)) == 7
     assert fused(spaced(7), cfg=B.config(tile_j=2, prefetch=8, nontemporal=1, schedule=3)) == 7
 
 

@@ -143,7 +143,8 @@ def test_config3_full_size(dtype, n):
 
 @pytest.mark.parametrize("tj,pf,nt,sched", [(2, 4, -1, 1), (4, 4, -1, 1), (2, 2, -1, 1), (2, 8, -1, 1),
                                             (1, 4, -1, 1), (2, 4, 1, 1), (4, 4, 1, 1), (2, 8, 1, 1),
-                                            (2, 2, 1, 1), (2, 4, 1, 2), (2, 8, 1, 2), (2, 4, 1, 3)])
+                                            (2, 2, 1, 1), (2, 4, 1, 2), (2, 8, 1, 2), (2, 4, 1, 3),
+                                            (4, 4, 1, 2), (1, 4, 1, 2), (2, 2, 1, 2)])
 def test_fused_variants_are_bitwise_identical(tj, pf, nt, sched):
     ni, nj, nk = 200, 37, 80
     f = inputs.fields(ni, nj, nk, 2, seed=SEED + 4, storage="f32")
