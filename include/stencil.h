@@ -104,7 +104,10 @@ typedef struct {
                          of level s-2), 3 pipelined on a persistent grid (a
                          workgroup walks several tiles and requests the next
                          tile's first levels before storing the current
-                         one), 0 the library's choice */
+                         one), 4 four lanes per column, partitioned (for
+                         grids with few columns; FP32 and FP64, nk >= 8),
+                         0 the library's choice (four lanes below 65536
+                         columns when no other knob is set) */
 } stencil_config_t;
 
 /* Horizontal diffusion, per level k and interior point (i, j):

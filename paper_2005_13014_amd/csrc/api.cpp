@@ -235,14 +235,37 @@ static bool column_variant(int dtype, const ColumnVariant &v) {
 // four levels prefetched, non-temporal streams, pipelined schedule).  A
 // non-zero knob that names no compiled variant is an error, not a silent
 // substitution.
-static int fused_variant(int dtype, const stencil_config_t &cf, ColumnVariant *out) {
+// Grids with fewer columns than this fill fewer than two waves per SIMD at two
+// lanes per column; the library then takes four lanes per column.
+constexpr long long SMALL_GRID_COLUMNS = 65536;
+
+static int fused_variant(int dtype, const stencil_config_t &cf, const stencil_field_t *u,
+                         ColumnVariant *out) {
     ColumnVariant v{};
-    v.tile_j = cf.tile_j ? cf.tile_j : 2;
-    v.prefetch = cf.prefetch ? cf.prefetch : dtype == STENCIL_F64 ? 2 : 4;
     if (cf.nontemporal < -1 || cf.nontemporal > 1)
         return fail(STENCIL_E_ARG, "nontemporal must be -1, 0 or 1 (got %d)", cf.nontemporal);
-    if (cf.schedule < 0 || cf.schedule > 3)
-        return fail(STENCIL_E_ARG, "schedule must be 0, 1, 2 or 3 (got %d)", cf.schedule);
+    if (cf.schedule < 0 || cf.schedule > SCHED_FOUR)
+        return fail(STENCIL_E_ARG, "schedule must be 0 .. 4 (got %d)", cf.schedule);
+    // Four lanes per column: asked for, or the library's choice on a small grid
+    // when no other knob is set.  It needs nk >= 8.
+    const bool knobs = cf.tile_j || cf.prefetch || cf.nontemporal;
+    const bool small = static_cast<long long>(u->ni) * u->nj < SMALL_GRID_COLUMNS;
+    if (cf.schedule == SCHED_FOUR || (cf.schedule == 0 && !knobs && small && u->nk >= 8)) {
+        v.tile_j = cf.tile_j ? cf.tile_j : 1;
+        v.prefetch = cf.prefetch ? cf.prefetch : dtype == STENCIL_F64 ? 2 : 4;
+        v.nt = cf.nontemporal >= 0;
+        v.sched = SCHED_FOUR;
+        if (column_variant(dtype, v) && (u->nk >= 8 || empty(u))) {
+            *out = v;
+            return STENCIL_OK;
+        }
+        if (cf.schedule == SCHED_FOUR)
+            return fail(STENCIL_E_UNSUPPORTED,
+                        "four lanes per column need FP32 or FP64 storage, nk >= 8, tile_j 1, prefetch 4 "
+                        "(FP64: 2) and non-temporal streams");
+    }
+    v.tile_j = cf.tile_j ? cf.tile_j : 2;
+    v.prefetch = cf.prefetch ? cf.prefetch : dtype == STENCIL_F64 ? 2 : 4;
     const bool nts[2] = {true, false};
     const int order[3] = {SCHED_PIPELINED, SCHED_PERSISTENT, SCHED_STAGED};  // library preference
     bool found = false;
@@ -408,7 +431,7 @@ STENCIL_API int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field
         return fail(STENCIL_E_ARG, "unknown level %d", cf.level);
     const int dtype = u->dtype;
     ColumnVariant var{};
-    TRY(fused_variant(dtype, cf, &var));
+    TRY(fused_variant(dtype, cf, u, &var));
     if (empty(u)) return STENCIL_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (cf.level == STENCIL_LEVEL_ORIGINAL || u->nk > KMAX_COLUMN || !column_fits(u)) {

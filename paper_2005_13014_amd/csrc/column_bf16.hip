@@ -1,5 +1,6 @@
 // Column kernels (column.hpp) instantiated for bfloat16 storage.
 #include "column.hpp"
+
 #include "launch.hpp"
 
 namespace stl {
@@ -43,6 +44,7 @@ static const ColumnEntry kFused[] = {
 };
 
 bool column_variant_bf16(const ColumnVariant &v) {
+    if (v.sched == SCHED_FOUR) return false;
     return find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.sched) != nullptr;
 }
 

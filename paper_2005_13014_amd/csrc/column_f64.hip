@@ -1,5 +1,6 @@
-// Column kernels (column.hpp) instantiated for double storage.
+// Column kernels (column.hpp, column4.hpp) instantiated for double storage.
 #include "column.hpp"
+#include "column4.hpp"
 #include "launch.hpp"
 
 namespace stl {
@@ -34,6 +35,17 @@ static hipError_t pipelined(const ColumnArgs &a, hipStream_t st) {
                      : launch_column_pipe_t<double, TJ, PF, 48, 1, NT, false, CHAIN>(a, st);
 }
 
+// Four lanes per column: segments of ceil(nk / 4) <= KH levels, nk >= 8,
+// 2 levels prefetched.
+static hipError_t four_lanes(const ColumnArgs &a, hipStream_t st) {
+    const int m = (a.K + 3) / 4;
+    if (m <= 8) return launch_column4_t<double, 2, 8, true>(a, st);
+    if (m <= 12) return launch_column4_t<double, 2, 12, true>(a, st);
+    if (m <= 16) return launch_column4_t<double, 2, 16, true>(a, st);
+    if (m <= 20) return launch_column4_t<double, 2, 20, true>(a, st);
+    return launch_column4_t<double, 2, 24, true>(a, st);
+}
+
 static const ColumnEntry kFused[] = {
     {2, 2, false, 1, staged<true, 2, 2, false>},
     {2, 4, false, 1, staged<true, 2, 4, false>},
@@ -42,11 +54,13 @@ static const ColumnEntry kFused[] = {
 };
 
 bool column_variant_f64(const ColumnVariant &v) {
+    if (v.sched == SCHED_FOUR) return v.tile_j == 1 && v.prefetch == 2 && v.nt;
     return find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.sched) != nullptr;
 }
 
 hipError_t launch_column_f64(bool fused, const ColumnArgs &a, const ColumnVariant &v, hipStream_t st) {
     if (!fused) return staged<false, 2, 2, false>(a, st);
+    if (v.sched == SCHED_FOUR) return four_lanes(a, st);
     const ColumnEntry *e = find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.sched);
     return e ? e->launch(a, st) : hipErrorInvalidValue;
 }

@@ -14,10 +14,11 @@ enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
 // nk <= KMAX_COLUMN.  A fused variant is chosen by rows per workgroup,
 // levels prefetched, non-temporal streams and the level-loop schedule
 // (staged; pipelined, so hdiff of one level overlaps the elimination of an
-// earlier one; or pipelined on a persistent grid that chains tiles); only the
-// compiled combinations are accepted.
+// earlier one; pipelined on a persistent grid that chains tiles; or four
+// lanes per column, partitioned, for small grids); only the compiled
+// combinations are accepted.
 constexpr int KMAX_COLUMN = 96;
-enum { SCHED_STAGED = 1, SCHED_PIPELINED = 2, SCHED_PERSISTENT = 3 };
+enum { SCHED_STAGED = 1, SCHED_PIPELINED = 2, SCHED_PERSISTENT = 3, SCHED_FOUR = 4 };
 struct ColumnVariant {
     int tile_j, prefetch;
     bool nt;

@@ -181,7 +181,9 @@ def test_scalar_and_config_checks():
     assert fused(spaced(7), dt=float("nan")) == 9
     assert vadv(spaced(6), dt=float("inf")) == 9
     assert fused(spaced(7), cfg=B.config(tile_j=3, prefetch=4)) == 7
-    assert fused(spaced(7), cfg=B.config(schedule=4)) == 9
+    assert fused(spaced(7), cfg=B.config(schedule=5)) == 9
+    # four lanes per column need nk >= 8 (these fields have 5 levels)
+    assert fused(spaced(7), cfg=B.config(schedule=4)) == 7
     assert fused(spaced(7), cfg=B.config(schedule=-1)) == 9
     assert fused(spaced(7), cfg=B.config(nontemporal=2)) == 9
     # a compiled tile shape with a schedule it is not compiled for

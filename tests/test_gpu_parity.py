@@ -148,7 +148,7 @@ def test_config3_full_size(dtype, n):
 def test_fused_variants_are_bitwise_identical(tj, pf, nt, sched):
     ni, nj, nk = 200, 37, 80
     f = inputs.fields(ni, nj, nk, 2, seed=SEED + 4, storage="f32")
-    base = run_hdiff_vadv(f, ni, nj, nk, 2, "f32").to_numpy(interior=True)
+    base = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(schedule=1)).to_numpy(interior=True)
     cfg = B.config(tile_j=tj, prefetch=pf, nontemporal=nt, schedule=sched)
     got = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=cfg)
     assert np.array_equal(got.to_numpy(interior=True), base)
@@ -172,6 +172,34 @@ def test_other_storage_variants_are_bitwise_identical(dtype, tj, pf, nt, nk):
             continue
         assert np.array_equal(x.to_numpy(interior=True), base), sched
         assert halo_untouched(x)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nk", [8, 9, 13, 31, 33, 60, 64, 79, 80, 81, 90, 96])
+def test_four_lanes_per_column(dtype, nk):
+    """The partitioned solve over four segments per column (schedule 4):
+    every depth from the shortest segments (two rows) to the deepest bucket,
+    on ragged tiles, against the oracle; halos untouched."""
+    ni, nj = 70, 6
+    f = inputs.fields(ni, nj, nk, 2, seed=SEED + 90 + nk, storage=dtype)
+    x = run_hdiff_vadv(f, ni, nj, nk, 2, dtype, cfg=B.config(schedule=4))
+    got = x.to_numpy(interior=True)
+    ref = ref_hdiff_vadv(f, 2)
+    e = normwise(got, ref)
+    note("four lanes %s nk=%d normwise %.2e" % (dtype, nk, e))
+    assert e <= TOL[dtype] and rms_rel(got, ref) <= TOL[dtype]
+    assert halo_untouched(x)
+
+
+def test_four_lanes_need_eight_levels():
+    ni, nj, nk = 64, 4, 7
+    f = inputs.fields(ni, nj, nk, 2, seed=SEED + 89, storage="f32")
+    with pytest.raises(B.StencilError) as ei:
+        run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(schedule=4))
+    assert ei.value.status == "E_UNSUPPORTED"
+    # the library's own choice falls back to two lanes per column
+    x = run_hdiff_vadv(f, ni, nj, nk, 2, "f32")
+    assert normwise(x.to_numpy(interior=True), ref_hdiff_vadv(f, 2)) <= TOL["f32"]
 
 
 @pytest.mark.parametrize("nk", [1, 2, 3, 4, 5, 9, 31, 32, 33, 64, 65, 79, 80, 81, 96])
