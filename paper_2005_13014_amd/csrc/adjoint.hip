@@ -262,7 +262,7 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
 // and gcoeff = -gh (flx - flx(i-1) + fly - fly(j-1)).
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ __launch_bounds__(256) void k_hdiff_adjoint(AdjArgs p, int nbi) {
+__global__ __launch_bounds__(256) void k_hdiff_adjoint(AdjArgs p, int nbi, int ntiles) {
     using S = Storage<T>;
     using C = typename S::C;
     constexpr int TI = 64, TJ = 4;
@@ -280,7 +280,11 @@ __global__ __launch_bounds__(256) void k_hdiff_adjoint(AdjArgs p, int nbi) {
     T *__restrict__ gu = static_cast<T *>(p.gu);
     T *__restrict__ gcoeff = static_cast<T *>(p.gcoeff);
     const int I = p.I, J = p.J, sj = p.sj;
-    const int bi = blockIdx.x % nbi, bj = blockIdx.x / nbi, k = blockIdx.y;
+    // Workgroups numbered level-major: consecutive positions are neighbouring
+    // tiles of one level, kept on one XCD so their shared halo rows meet in its L2.
+    const int pos = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = pos % ntiles, k = pos / ntiles;
+    const int bi = tile % nbi, bj = tile / nbi;
     const int x0 = -2 + bi * TI, y0 = -2 + bj * TJ;
     const int ko = k * p.sk;
     const int tid = threadIdx.x;
@@ -390,7 +394,10 @@ static hipError_t adjoint_run(AdjArgs a, void *scratch, hipStream_t st) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nbi = (a.I + 4 + 63) / 64, nbj = (a.J + 4 + 3) / 4;
-    hipLaunchKernelGGL((k_hdiff_adjoint<T>), dim3(nbi * nbj, a.K), dim3(256), 0, st, a, nbi);
+    const long long blocks = static_cast<long long>(nbi) * nbj * a.K;
+    if (blocks > 2147483647LL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_hdiff_adjoint<T>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a, nbi,
+                       nbi * nbj);
     return hipGetLastError();
 }
 
