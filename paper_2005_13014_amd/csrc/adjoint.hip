@@ -249,23 +249,23 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
 }
 
 // ---------------------------------------------------------------------------
-// hdiff adjoint.  Tile of 64 x 4 output points of the extended domain
+// hdiff adjoint.  Tile of 64 x TJ output points of the extended domain
 // [-2, I+2) x [-2, J+2) at one level, local coordinates (lx, ly) = (i - x0,
 // j - y0).  Stages (each ends with a barrier):
-//   U  u on lx in [-3, 67), ly in [-3, 7) (0 outside u's 2-cell halo)
-//   G  g = -coeff gh on lx in [-2, 66), ly in [-2, 6) (0 outside the interior)
-//   L  lap on lx in [-2, 66), ly in [-2, 6)
-//   X  x-faces lx in [-2, 65), ly in [-1, 5): gfx = kx (g(i) - g(i+1)), flx = kx (lap(i+1) - lap(i))
-//   Y  y-faces lx in [-1, 65), ly in [-2, 5): likewise in j
-//   H  glap = gfx(i-1) - gfx(i) + gfy(j-1) - gfy(j) on lx in [-1, 65), ly in [-1, 5)
+//   U  u on lx in [-3, 67), ly in [-3, TJ+3) (0 outside u's 2-cell halo)
+//   G  g = -coeff gh on lx in [-2, 66), ly in [-2, TJ+2) (0 outside the interior)
+//   L  lap on lx in [-2, 66), ly in [-2, TJ+2)
+//   X  x-faces lx in [-2, 65), ly in [-1, TJ+1): gfx = kx (g(i) - g(i+1)), flx = kx (lap(i+1) - lap(i))
+//   Y  y-faces lx in [-1, 65), ly in [-2, TJ+1): likewise in j
+//   H  glap = gfx(i-1) - gfx(i) + gfy(j-1) - gfy(j) on lx in [-1, 65), ly in [-1, TJ+1)
 // then gu = gh (interior) - glap(j-1) - glap(i-1) + 4 glap - glap(i+1) - glap(j+1)
 // and gcoeff = -gh (flx - flx(i-1) + fly - fly(j-1)).
 // ---------------------------------------------------------------------------
-template <class T>
+template <class T, int TJ>
 __global__ __launch_bounds__(256) void k_hdiff_adjoint(AdjArgs p, int nbi, int ntiles) {
     using S = Storage<T>;
     using C = typename S::C;
-    constexpr int TI = 64, TJ = 4;
+    constexpr int TI = 64;
     constexpr int UX = TI + 6, UY = TJ + 6;     // offset 3
     constexpr int GX = TI + 4, GY = TJ + 4;     // offset 2 (g and lap)
     constexpr int XX = TI + 3, XY = TJ + 2;     // x-faces: lx + 2, ly + 1
@@ -333,8 +333,8 @@ __global__ __launch_bounds__(256) void k_hdiff_adjoint(AdjArgs p, int nbi, int n
         sh[e] = sgx[xi - 1] - sgx[xi] + sgy[yi - YX] - sgy[yi];
     }
     __syncthreads();
-    {
-        const int lx = tid & 63, ly = tid >> 6;
+    for (int ly = tid >> 6; ly < TJ; ly += 4) {
+        const int lx = tid & 63;
         const int i = x0 + lx, j = y0 + ly;
         if (i < I + 2 && j < J + 2) {
             const int hc = (ly + 1) * HX + lx + 1;
@@ -393,11 +393,14 @@ static hipError_t adjoint_run(AdjArgs a, void *scratch, hipStream_t st) {
     else launch_vadv_adjoint_t<T, 48>(a, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int nbi = (a.I + 4 + 63) / 64, nbj = (a.J + 4 + 3) / 4;
+    // Rows per hdiff-adjoint tile: 8 (two per thread) where the staged tile
+    // fits often enough in LDS; FP64's twice larger tile keeps 4.
+    constexpr int HTJ = std::is_same<T, double>::value ? 4 : 8;
+    const int nbi = (a.I + 4 + 63) / 64, nbj = (a.J + 4 + HTJ - 1) / HTJ;
     const long long blocks = static_cast<long long>(nbi) * nbj * a.K;
     if (blocks > 2147483647LL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_hdiff_adjoint<T>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a, nbi,
-                       nbi * nbj);
+    hipLaunchKernelGGL((k_hdiff_adjoint<T, HTJ>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a,
+                       nbi, nbi * nbj);
     return hipGetLastError();
 }
 
