@@ -25,37 +25,76 @@ struct HgradBatch {
     double beta_h, beta_v;
 };
 
+// One 64 x 4 tile of one field per workgroup, marching k.  Per level the
+// tile's y rows j0 - 1 .. j0 + 4 and its side columns i0 - 1, i0 + 64 are
+// staged in LDS (each wave loads its own row, which holds its centre values;
+// waves 0 and 1 also load the rows above and below the tile, wave 2 the side
+// columns), the horizontal neighbours are read from the tile and the vertical
+// ones are kept in registers.  Loads run two levels ahead.
 template <class T>
 __global__ __launch_bounds__(256) void k_hgrad_batch(HgradBatch b) {
     using S = Storage<T>;
     using C = typename S::C;
     using IO = BufIO<T>;
+    constexpr int PI = 68, ROWS = 6, TILE = ROWS * PI;
     constexpr uint32_t ES = sizeof(T);
+    __shared__ C tile[2 * TILE];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     int s = 0;
     while (s + 1 < b.nsub && b.sub[s + 1].tile0 <= t) ++s;
     const HgradSub &sb = b.sub[s];
     const int local = t - sb.tile0;
-    const int f = local % sb.nfields, tile = local / sb.nfields;
-    const int bi = tile % sb.nbi, bj = tile / sb.nbi;
-    const int gi = bi * 64 + (threadIdx.x & 63), gj = bj * 4 + (threadIdx.x >> 6);
-    if (gi >= sb.I || gj >= sb.J) return;
-    const int sj = sb.sj, K = sb.K;
-    // y is addressed from its cell (-1, -1, 0).
-    const auto ry = make_rsrc(static_cast<const char *>(sb.y[f]) - (1 + sj) * static_cast<int>(ES),
-                              sb.y_bytes);
+    const int f = local % sb.nfields, tl = local / sb.nfields;
+    const int bi = tl % sb.nbi, bj = tl / sb.nbi;
+    const int tid = threadIdx.x, ti = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int I = sb.I, J = sb.J, sj = sb.sj, K = sb.K;
+    const int i0 = bi * 64, j0 = bj * 4;
+    const int gi = i0 + ti, gj = j0 + w;
+    const bool active = gi < I && gj < J;
+    // y is addressed from its cell (-1, -1, 0); cells are clamped into
+    // [-1, I] x [-1, J], which only lanes that store nothing can reach.
+    const auto ry = make_rsrc(static_cast<const char *>(sb.y[f]) - (1 + sj) * static_cast<int>(ES), sb.y_bytes);
     const auto rz = make_rsrc(sb.z[f], sb.z_bytes);
-    const uint32_t vc = static_cast<uint32_t>(gi + 1 + (gj + 1) * sj) * ES;
-    const uint32_t ve = vc + ES, vw = vc - ES, vn = vc + sj * ES, vs = vc - sj * ES;
-    const uint32_t vz = static_cast<uint32_t>(gi + gj * sj) * ES;
+    auto voff = [&](int i, int j) {
+        return static_cast<uint32_t>(min(max(i, -1), I) + 1 + (min(max(j, -1), J) + 1) * sj) * ES;
+    };
+    const uint32_t v_own = voff(gi, gj);
+    // Second row: wave 0 the row above the tile (tile row 0), wave 1 the row
+    // below it (tile row 5), wave 2 the side columns (lanes 0 .. 11), wave 3 none.
+    const int sr = ti >> 1, scol = (ti & 1) ? 65 : 0;  // side: tile row, tile column
+    const uint32_t v_two = w == 0 ? voff(gi, j0 - 1) : w == 1 ? voff(gi, j0 + 4) : voff(i0 - 1 + scol, j0 - 1 + min(sr, ROWS - 1));
+    const bool two = w < 2 || (w == 2 && ti < 2 * ROWS);
+    const int l_own = (w + 1) * PI + ti + 1;
+    const int l_two = w == 0 ? ti + 1 : w == 1 ? 5 * PI + ti + 1 : min(sr, ROWS - 1) * PI + scol;
+    const uint32_t vz = static_cast<uint32_t>(min(gi, I - 1) + min(gj, J - 1) * sj) * ES;
     const uint32_t skb = static_cast<uint32_t>(sb.sk) * ES;
+
+    // Register ring rotated every level: (own0, two0) hold level k, (own1, two1) level k + 1.
+    C own0 = C(0), two0 = C(0), own1 = C(0), two1 = C(0);
+    auto load = [&](C &own, C &tw, int k) {
+        const uint32_t so = static_cast<uint32_t>(k) * skb;
+        own = IO::load(ry, v_own, so);
+        if (two) tw = IO::load(ry, v_two, so);
+    };
+    load(own0, two0, 0);
+    if (K > 1) load(own1, two1, 1);
+
     const C bh = static_cast<C>(b.beta_h), bv = static_cast<C>(b.beta_v), half = C(0.5);
-    C y_dn = C(0), y_c = IO::load(ry, vc, 0);
+    C y_dn = C(0), y_c = own0;
     for (int k = 0; k < K; ++k) {
-        const uint32_t so = k * skb;
-        const C y_up = k + 1 < K ? IO::load(ry, vc, so + skb) : C(0);
-        const C gi_ = half * (IO::load(ry, ve, so) - IO::load(ry, vw, so));
-        const C gj_ = half * (IO::load(ry, vn, so) - IO::load(ry, vs, so));
+        C *tb = &tile[(k & 1) * TILE];
+        tb[l_own] = own0;
+        if (two) tb[l_two] = two0;
+        const C y_up = k + 1 < K ? own1 : C(0);
+        // rotate: level k + 1 moves down, level k + 2 is requested
+        own0 = own1;
+        two0 = two1;
+        if (k + 2 < K) load(own1, two1, k + 2);
+        __syncthreads();
+        const C *c = &tb[(w + 1) * PI + ti + 1];
+        const C gi_ = half * (c[1] - c[-1]);
+        const C gj_ = half * (c[PI] - c[-PI]);
         C gk;
         if (K == 1)
             gk = C(0);
@@ -66,7 +105,7 @@ __global__ __launch_bounds__(256) void k_hgrad_batch(HgradBatch b) {
         else
             gk = half * (y_up - y_dn);
         const C z = y_c - bh * (gi_ + gj_) - bv * gk;
-        IO::store_d(rz, vz, so, static_cast<double>(z));
+        if (active) IO::template store_d<2>(rz, vz, static_cast<uint32_t>(k) * skb, static_cast<double>(z));
         y_dn = y_c;
         y_c = y_up;
     }
