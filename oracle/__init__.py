@@ -184,6 +184,17 @@ def vdiff(x, hx, kappa, e=0):
     return y
 
 
+def vdiff_implicit(x, hx, kappa, e=0):
+    """Implicit vertical diffusion with zero-flux ends (a tridiagonal solve per column)."""
+    lib = _load()
+    x = _f64(x)
+    ni, nj, nk = _dims(x, hx)
+    y = padded(ni, nj, nk, e)
+    _check(lib.oracle_vdiff_implicit(_I(ni), _I(nj), _I(nk), _dp(x), _I(hx), _DBL(kappa), _dp(y),
+                                     _I(e), _I(e)), "vdiff_implicit")
+    return y
+
+
 def hgrad(y, hy, beta_h, beta_v, e=0):
     lib = _load()
     y = _f64(y)
@@ -194,15 +205,18 @@ def hgrad(y, hy, beta_h, beta_v, e=0):
     return z
 
 
-def timestep(u, hu, coeff, hcf, w, hw, a, ha, b, hb, c, hc, dt, kappa, beta_h, beta_v):
-    """One field of the batched timestep: hdiff -> vadv -> vdiff -> hgrad."""
+def timestep(u, hu, coeff, hcf, w, hw, a, ha, b, hb, c, hc, dt, kappa, beta_h, beta_v,
+             implicit=False):
+    """One field of the batched timestep: hdiff -> vadv -> vdiff (explicit or
+    implicit) -> hgrad."""
     lib = _load()
     u, coeff, w, a, b, c = map(_f64, (u, coeff, w, a, b, c))
     ni, nj, nk = _dims(u, hu)
     z = padded(ni, nj, nk, 0)
-    _check(lib.oracle_timestep(_I(ni), _I(nj), _I(nk), _dp(u), _I(hu), _dp(coeff), _I(hcf), _dp(w),
-                               _I(hw), _dp(a), _I(ha), _dp(b), _I(hb), _dp(c), _I(hc), _DBL(dt),
-                               _DBL(kappa), _DBL(beta_h), _DBL(beta_v), _dp(z), _I(0)), "timestep")
+    _check(lib.oracle_timestep_ex(_I(ni), _I(nj), _I(nk), _dp(u), _I(hu), _dp(coeff), _I(hcf),
+                                  _dp(w), _I(hw), _dp(a), _I(ha), _dp(b), _I(hb), _dp(c), _I(hc),
+                                  _DBL(dt), _DBL(kappa), _DBL(beta_h), _DBL(beta_v),
+                                  _I(1 if implicit else 0), _dp(z), _I(0)), "timestep")
     return z
 
 

@@ -337,6 +337,36 @@ int oracle_vdiff(int ni, int nj, int nk, const double *x, int hx, double kappa, 
     return OK;
 }
 
+/* Implicit (backward-Euler) 3-point vertical diffusion with zero-flux bottom
+ * and top faces: y solves y(k) - kappa (G(k+1/2) - G(k-1/2)) = x(k) with
+ * G(k+1/2) = y(k+1) - y(k) inside the column and G = 0 through its two end
+ * faces, i.e. the tridiagonal system -kappa y(k-1) + (1 + 2 kappa) y(k)
+ * - kappa y(k+1) = x(k) whose end rows lose the kappa of the missing face.
+ * Solved per column by the Thomas algorithm. */
+int oracle_vdiff_implicit(int ni, int nj, int nk, const double *x, int hx, double kappa, double *y,
+                          int hy, int e)
+{
+    if (bad_dims(ni, nj, nk) || e < 0 || hx < e || hy < e) return ERR_ARG;
+    if (nk == 0) return OK;
+    double *col = (double *)malloc((size_t)nk * 7 * sizeof(double));
+    if (!col) return ERR_MEM;
+    double *sub = col, *diag = col + nk, *sup = col + 2 * nk, *rhs = col + 3 * nk, *out = col + 4 * nk;
+    double *cp = col + 5 * nk, *dp = col + 6 * nk;
+    for (int k = 0; k < nk; ++k) {
+        sub[k] = k > 0 ? -kappa : 0.0;
+        sup[k] = k + 1 < nk ? -kappa : 0.0;
+        diag[k] = 1.0 + (k > 0 ? kappa : 0.0) + (k + 1 < nk ? kappa : 0.0);
+    }
+    for (int j = -e; j < nj + e; ++j)
+        for (int i = -e; i < ni + e; ++i) {
+            for (int k = 0; k < nk; ++k) rhs[k] = x[idx(ni, nj, hx, i, j, k)];
+            thomas_column(nk, sub, diag, sup, rhs, 1, out, cp, dp);
+            for (int k = 0; k < nk; ++k) y[idx(ni, nj, hy, i, j, k)] = out[k];
+        }
+    free(col);
+    return OK;
+}
+
 /* 7-point horizontal-gradient update: centred differences in i and j, centred
  * in k inside the column and one-sided at its two ends.  Needs hy >= e + 1. */
 int oracle_hgrad(int ni, int nj, int nk, const double *y, int hy, double beta_h, double beta_v,
@@ -365,11 +395,12 @@ int oracle_hgrad(int ni, int nj, int nk, const double *y, int hy, double beta_h,
 
 /* One field of the batched timestep: hdiff -> vadv -> vdiff on the interior
  * grown by one cell (the ring hgrad reads), then hgrad on the interior.
+ * implicit != 0 takes the implicit vertical diffusion.
  * u needs halo >= 3, the coefficient fields halo >= 1. */
-int oracle_timestep(int ni, int nj, int nk, const double *u, int hu, const double *coeff, int hcf,
-                    const double *w, int hw, const double *a, int ha, const double *b, int hb,
-                    const double *c, int hc, double dt, double kappa, double beta_h, double beta_v,
-                    double *z, int hz)
+int oracle_timestep_ex(int ni, int nj, int nk, const double *u, int hu, const double *coeff, int hcf,
+                       const double *w, int hw, const double *a, int ha, const double *b, int hb,
+                       const double *c, int hc, double dt, double kappa, double beta_h,
+                       double beta_v, int implicit, double *z, int hz)
 {
     if (bad_dims(ni, nj, nk)) return ERR_ARG;
     size_t n = padded_size(ni, nj, nk, 1);
@@ -380,10 +411,21 @@ int oracle_timestep(int ni, int nj, int nk, const double *u, int hu, const doubl
         return ERR_MEM;
     }
     int rc = oracle_hdiff_vadv(ni, nj, nk, u, hu, coeff, hcf, w, hw, a, ha, b, hb, c, hc, dt, x, 1, 1);
-    if (rc == OK) rc = oracle_vdiff(ni, nj, nk, x, 1, kappa, y, 1, 1);
+    if (rc == OK)
+        rc = implicit ? oracle_vdiff_implicit(ni, nj, nk, x, 1, kappa, y, 1, 1)
+                      : oracle_vdiff(ni, nj, nk, x, 1, kappa, y, 1, 1);
     if (rc == OK) rc = oracle_hgrad(ni, nj, nk, y, 1, beta_h, beta_v, z, hz, 0);
     free(x); free(y);
     return rc;
+}
+
+int oracle_timestep(int ni, int nj, int nk, const double *u, int hu, const double *coeff, int hcf,
+                    const double *w, int hw, const double *a, int ha, const double *b, int hb,
+                    const double *c, int hc, double dt, double kappa, double beta_h, double beta_v,
+                    double *z, int hz)
+{
+    return oracle_timestep_ex(ni, nj, nk, u, hu, coeff, hcf, w, hw, a, ha, b, hb, c, hc, dt, kappa,
+                              beta_h, beta_v, 0, z, hz);
 }
 
 /* ------------------------------------------------------------------------ */

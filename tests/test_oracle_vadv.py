@@ -196,6 +196,46 @@ def test_vdiff_invariants():
     assert np.allclose(yq[1:-1], quad[1:-1] + 2 * kappa, rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("nk", [1, 2, 3, 8, 40])
+def test_vdiff_implicit_pins(nk):
+    """Backward-Euler vertical diffusion: conserves the column sum (zero-flux
+    ends), keeps constants, agrees with a dense solve of the same matrix, and
+    the explicit operator applied to its result gives back the input."""
+    kappa = 0.1
+    rng = np.random.default_rng(40 + nk)
+    x = rng.uniform(-1, 1, (nk, 3, 2))
+    y = oracle.vdiff_implicit(x, 0, kappa)
+    assert np.abs(y.sum(axis=0) - x.sum(axis=0)).max() <= 1e-13 * nk
+    c = np.full((nk, 2, 2), -2.25)
+    assert np.allclose(oracle.vdiff_implicit(c, 0, kappa), c, rtol=0, atol=1e-14)
+    # dense matrix of (I - kappa L), L the zero-flux Laplacian along k
+    A = np.eye(nk)
+    for k in range(nk):
+        if k > 0:
+            A[k, k - 1] -= kappa
+            A[k, k] += kappa
+        if k + 1 < nk:
+            A[k, k + 1] -= kappa
+            A[k, k] += kappa
+    for j in range(3):
+        for i in range(2):
+            assert np.allclose(y[:, j, i], np.linalg.solve(A, x[:, j, i]), rtol=0, atol=1e-14)
+    # y - kappa L y = x: the explicit operator with -kappa undoes the implicit one
+    back = oracle.vdiff(y, 0, -kappa)
+    assert np.allclose(back, x, rtol=0, atol=1e-14)
+
+
+def test_timestep_implicit_is_the_chain():
+    ni, nj, nk, h = 7, 6, 9, 3
+    f = inputs.fields(ni, nj, nk, h, seed=52)
+    args = (f["u"], h, f["coeff"], h, f["wcon"], h, f["a"], h, f["b"], h, f["c"], h, 10.0)
+    z = oracle.timestep(*args, 0.1, 0.05, 0.01, implicit=True)
+    x = oracle.hdiff_vadv(*args, e=1)
+    y = oracle.vdiff_implicit(x, 1, 0.1, e=1)
+    assert np.array_equal(z, oracle.hgrad(y, 1, 0.05, 0.01))
+    assert not np.array_equal(z, oracle.timestep(*args, 0.1, 0.05, 0.01))
+
+
 @pytest.mark.parametrize("al,be,ga", [(0.5, -1.25, 2.0), (1.0, 0.0, -3.0)])
 def test_hgrad_linear_field(al, be, ga):
     ni, nj, nk, bh, bv = 6, 5, 7, 0.05, 0.01
