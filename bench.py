@@ -202,9 +202,10 @@ def variant_hdiff_levels(ni, nj, nk):
     return out
 
 
-def variant_program():
+def variant_program(implicit=False):
     """The batched timestep: hdiff -> vadv -> vdiff -> hgrad on 8 fields over
-    6 uneven subdomains, FP32, hipGraph + autotuned variant."""
+    6 uneven subdomains, FP32, hipGraph + autotuned variant; implicit takes
+    the implicit vertical diffusion (a second tridiagonal solve per column)."""
     import torch
     from paper_2005_13014_amd import binding as B
     from paper_2005_13014_amd import inputs
@@ -223,7 +224,9 @@ def variant_program():
         pts += ni * nj * nk * nf
         # per field: u (3-ring diamond of the grown domain ~ interior) + z; shared coefficients once
         nbytes += 4 * (nf * 2 * ni * nj * nk + 5 * ni * nj * nk)
-    spec = B.ProgramSpec(subs, dt=DT, flags=B.PROGRAM_GRAPH | B.PROGRAM_AUTOTUNE)
+    stages = B.STAGE_HDIFF | B.STAGE_VADV | B.STAGE_HGRAD | (
+        B.STAGE_VDIFF_IMPLICIT if implicit else B.STAGE_VDIFF)
+    spec = B.ProgramSpec(subs, stages=stages, dt=DT, flags=B.PROGRAM_GRAPH | B.PROGRAM_AUTOTUNE)
     w, k = time_calls(lambda _: B.stencil_program_run(spec), [None], 20, 3)
     del subs
     torch.cuda.empty_cache()
@@ -359,6 +362,70 @@ def summarize_profiles(outdir):
     print("\n".join(md))
 
 
+VARIANT_TRACE_CMD = ("cd /tmp && TMPDIR=/tmp rocprofv3 --kernel-trace --stats --output-format csv "
+                     "-d $R/gpurun_out/v_{v}_trace -o t -- python $R/bench.py --only {v}")
+VARIANT_PMC_CMD = ("cd /tmp && TMPDIR=/tmp timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv "
+                   "-d $R/gpurun_out/v_{v}_{t} -o t -- python $R/bench.py --only {v}")
+
+
+def summarize_variant(outdir, name, fetch_calibration):
+    """Writes profiles/variant_<name>.md: per-kernel times of bench.py --only
+    <name> from its kernel trace, with the FETCH_SIZE / WRITE_SIZE counts of the
+    matching counter runs when present (FETCH scaled by the copy-probe
+    calibration of the headline traffic summary)."""
+    import csv
+    import glob
+
+    def one(pattern):
+        hits = sorted(glob.glob(os.path.join(outdir, pattern), recursive=True))
+        return hits[0] if hits else None
+
+    def per_kernel(tag, cname):
+        f = one("v_%s_%s/**/*counter_collection.csv" % (name, tag))
+        out = {}
+        for r in csv.DictReader(open(f)) if f else []:
+            if r.get("Counter_Name") == cname:
+                out.setdefault(r["Kernel_Name"].split("(")[0], []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in out.items()}
+
+    rows = list(csv.DictReader(open(one("v_%s_trace/**/*kernel_stats.csv" % name))))
+    fe, wr = per_kernel("fetch", "FETCH_SIZE"), per_kernel("write", "WRITE_SIZE")
+    md = ["# Kernel trace: `bench.py --only %s`" % name, "",
+          "Commands (from the repository root `$R` on the GPU box):", "", "```",
+          VARIANT_TRACE_CMD.format(v=name)]
+    if fe:
+        md += [VARIANT_PMC_CMD.format(c="FETCH_SIZE", v=name, t="fetch"),
+               VARIANT_PMC_CMD.format(c="WRITE_SIZE", v=name, t="write")]
+    md += ["```", "", "| kernel | calls | average (us) | HBM read (MB) | HBM write (MB) | GB/s |",
+           "|---|---|---|---|---|---|"]
+    for r in rows:
+        n = r["Name"].split("(")[0]
+        if "stl::" not in n:
+            continue
+        us = float(r["AverageNs"]) / 1e3
+        rb = fe[n] * 1024 / fetch_calibration if n in fe else None
+        wb = wr[n] * 1024 if n in wr else None
+        gbs = (rb + wb) / (us * 1e-6) / 1e9 if rb is not None and wb is not None else None
+        md.append("| `%s` | %s | %.1f | %s | %s | %s |" % (
+            n, r["Calls"], us, "%.1f" % (rb / 1e6) if rb is not None else "-",
+            "%.1f" % (wb / 1e6) if wb is not None else "-", "%.0f" % gbs if gbs else "-"))
+    md += ["", "HBM read = FETCH_SIZE / %.3f (the copy-probe calibration), write = WRITE_SIZE; both per "
+           "dispatch.  Library sources hash %s." % (fetch_calibration, library_hash())]
+    path = os.path.join(ROOT, "profiles", "variant_%s.md" % name)
+    with open(path, "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
+def library_hash():
+    import glob
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2005_13014_amd", "csrc", "*"))):
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -374,7 +441,7 @@ def main():
                     help="only the headline measurement (no variants, no CPU baseline)")
     ap.add_argument("--with-copy", action="store_true",
                     help="with --quick: also run the copy probe (counter calibration)")
-    ap.add_argument("--only", choices=["timestep", "adjoint"],
+    ap.add_argument("--only", choices=["timestep", "timestep_implicit", "adjoint"],
                     help="run only this variant and print its figures (for profiling)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write the profile summaries under profiles/ from rocprofv3 output in DIR "
@@ -382,6 +449,17 @@ def main():
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles)
+        cal = 0.5
+        try:
+            with open(TRAFFIC_FILE) as fh:
+                cal = json.load(fh)["fetch_calibration"]
+        except (OSError, ValueError, KeyError):
+            pass
+        for v in ("timestep", "adjoint"):
+            import glob
+            if glob.glob(os.path.join(args.summarize_profiles, "v_%s_trace" % v, "**", "*kernel_stats.csv"),
+                         recursive=True):
+                summarize_variant(args.summarize_profiles, v, cal)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the stencil path runs on a single MI355X and no "
@@ -394,7 +472,8 @@ def main():
     dev = torch.cuda.get_device_properties(0)
     log("device:", dev.name, "CUs:", dev.multi_processor_count)
     if args.only:
-        fn = {"timestep": variant_program, "adjoint": variant_adjoint}[args.only]
+        fn = {"timestep": variant_program, "timestep_implicit": lambda: variant_program(implicit=True),
+              "adjoint": variant_adjoint}[args.only]
         print(json.dumps({"variant": args.only, "result": fn()}), flush=True)
         return
 
@@ -464,6 +543,9 @@ def main():
     torch.cuda.empty_cache()
     log("variant batched timestep")
     variants["timestep_6x8_f32"] = variant_program()
+    torch.cuda.empty_cache()
+    log("variant batched timestep, implicit vertical diffusion")
+    variants["timestep_6x8_f32_implicit_vdiff"] = variant_program(implicit=True)
     torch.cuda.empty_cache()
     log("variant adjoint 256x256x80")
     variants["adjoint_256x256x80"] = variant_adjoint()

@@ -185,9 +185,13 @@ enum {
     STENCIL_STAGE_VADV = 2,
     STENCIL_STAGE_VDIFF = 4,  /* y(k) = x(k) + kappa (x(k+1) - 2x(k) + x(k-1)),
                                  zero flux through the bottom and top faces */
-    STENCIL_STAGE_HGRAD = 8   /* z = y - beta_h ((y(i+1)-y(i-1))/2 + (y(j+1)-y(j-1))/2)
+    STENCIL_STAGE_HGRAD = 8,  /* z = y - beta_h ((y(i+1)-y(i-1))/2 + (y(j+1)-y(j-1))/2)
                                  - beta_v Dk y, Dk centred inside the column and
                                  one-sided at its two ends */
+    STENCIL_STAGE_VDIFF_IMPLICIT = 16 /* in place of VDIFF: y solves
+                                 y(k) - kappa (y(k+1) - 2y(k) + y(k-1)) = x(k),
+                                 zero flux through the bottom and top faces (a
+                                 second tridiagonal solve per column, FP64) */
 };
 
 /* One subdomain: nfields prognostic fields sharing coeff, wcon, a, b, c. */
@@ -200,7 +204,8 @@ typedef struct {
 
 /* A timestep program over independent subdomains of different sizes
  * (a stencil program with eager program-level control, Sec. IV-F).
- * stages: HDIFF|VADV, HDIFF|VADV|VDIFF or HDIFF|VADV|VDIFF|HGRAD.
+ * stages: HDIFF|VADV, HDIFF|VADV|VDIFF or HDIFF|VADV|VDIFF|HGRAD, or either
+ * of the last two with VDIFF_IMPLICIT in place of VDIFF.
  * Shape inference (Sec. V-B) derives the halos: with HGRAD the earlier stages
  * run on the interior grown by one cell, so u needs halo >= 3 and the shared
  * coefficient fields halo >= 1; otherwise u needs 2 and the coefficients 0. */

@@ -27,7 +27,7 @@ TORCH_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat1
 ELEM_SIZE = {"f64": 8, "f32": 4, "bf16": 2}
 
 LEVEL_DEFAULT, LEVEL_ORIGINAL, LEVEL_INLINE = 0, 1, 2
-STAGE_HDIFF, STAGE_VADV, STAGE_VDIFF, STAGE_HGRAD = 1, 2, 4, 8
+STAGE_HDIFF, STAGE_VADV, STAGE_VDIFF, STAGE_HGRAD, STAGE_VDIFF_IMPLICIT = 1, 2, 4, 8, 16
 PROGRAM_GRAPH, PROGRAM_AUTOTUNE = 1, 2
 
 STATUS = {0: "OK", 1: "E_NULL", 2: "E_DTYPE", 3: "E_SHAPE", 4: "E_STRIDE", 5: "E_HALO",

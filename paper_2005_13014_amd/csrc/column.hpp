@@ -106,9 +106,10 @@ __device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
 // ---------------------------------------------------------------------------
 // Workgroup = 2 halves x (64 x TJ lanes); the tile is 64 x TJ columns.
 // ---------------------------------------------------------------------------
-// One 64 x TJ tile of columns; VDIFF replaces x by y = x + kappa (x(k+1) -
+// One 64 x TJ tile of columns.  VD = 1 replaces x by y = x + kappa (x(k+1) -
 // 2 x(k) + x(k-1)) (zero flux through the bottom and top faces), finished
-// level by level during the back-substitution.
+// level by level during the back-substitution; VD = 2 by the implicit
+// counterpart, y - kappa (y(k+1) - 2 y(k) + y(k-1)) = x (same end faces).
 // NT: the read-once column inputs and the output use non-temporal accesses
 // (u is re-read by neighbouring tiles through L2 and keeps the default).
 // NTX: only the output is non-temporal (for column inputs that other
@@ -116,7 +117,7 @@ __device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
 // EXACT: nk == 2 KH, so both halves take exactly KH levels; every level
 // guard is then a compile-time constant and each barrier interval of the
 // level loop is one straight-line scheduling region.
-template <class T, bool FUSED, bool VDIFF, int TJ, int PF, int KH, bool NT = false, bool EXACT = false,
+template <class T, bool FUSED, int VD, int TJ, int PF, int KH, bool NT = false, bool EXACT = false,
           bool NTX = NT>
 __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj, double kappa) {
 #pragma clang fp contract(off)
@@ -299,7 +300,7 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     // elimination is local level tt - shift; the walk runs from the
     // interface (local level nsteps - 1) down to local level 0.
     double xn = half ? x_hi : x_lo;
-    if constexpr (!VDIFF) {
+    if constexpr (VD == 0) {
         if (active && nsteps > 0)
             IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, xn);
 #pragma unroll
@@ -310,7 +311,7 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
                     IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(tt - shift)) * sk_bytes, xn);
             }
         }
-    } else {
+    } else if constexpr (VD == 1) {
         // y at local level t + 1 is finished once x(t) is known: its neighbour
         // toward the interface is x(t + 2) (the other half's interface value
         // for t + 1 = nsteps - 1), away from it x(t).  Half 0 walks down
@@ -337,6 +338,63 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
             }
         }
         if (nsteps > 0) finish(0, x_in, nsteps > 1 || has_other, 0.0, false);
+    } else {
+        // Implicit vertical diffusion, y - kappa (G(k+1/2) - G(k-1/2)) = x with
+        // zero-flux end faces: a second, constant-coefficient tridiagonal
+        // solve over the same two-way split.  x(t) replaces D(t) as the walk
+        // produces it, then each half eliminates from its far end again
+        // (lower = the neighbour toward the far end, upper = toward the
+        // interface, both -kappa where they exist), the interface rows are
+        // solved as before and y is stored during the second walk outward.
+        D[KH - 1] = xn;
+#pragma unroll
+        for (int tt = KH - 2; tt >= 0; --tt)
+            if (tt >= shift) D[tt] = fmadd(-P[tt], D[tt + 1], D[tt]);
+        const bool toward_last = K - M > 0;  // the interface row has a neighbour across
+#pragma unroll
+        for (int st = 0; st < KH; ++st) {
+            const int t = st - shift;
+            const bool has_lo = t > 0, has_up = t < nsteps - 1 || toward_last;
+            double lo = has_lo ? -kappa : 0.0, up = has_up ? -kappa : 0.0;
+            double bd = 1.0 + (has_lo ? kappa : 0.0) + (has_up ? kappa : 0.0);
+            double xt = D[st];
+            if (t < 0) {  // padding row: identity with zero right-hand side
+                lo = 0.0;
+                up = 0.0;
+                bd = 1.0;
+                xt = 0.0;
+            }
+            if (st == 0) {
+                const double r = recip(bd);
+                P[0] = up * r;
+                D[0] = xt * r;
+            } else {
+                const int sm = st > 0 ? st - 1 : 0;
+                const double r = recip(fmadd(-lo, P[sm], bd));
+                P[st] = up * r;
+                D[st] = fmadd(-lo, D[sm], xt) * r;
+            }
+        }
+        const double Qm = nsteps > 0 ? P[KH - 1] : 0.0, Em = nsteps > 0 ? D[KH - 1] : 0.0;
+        __syncthreads();
+        xch[tid] = make_double2(Qm, Em);
+        __syncthreads();
+        const double2 o3 = xch[half ? l : NH + l];
+        const double Q0 = half ? o3.x : Qm, E0 = half ? o3.y : Em;
+        const double Q1 = half ? Qm : o3.x, E1 = half ? Em : o3.y;
+        const double y_lo = fmadd(-Q0, E1, E0) / fmadd(-Q0, Q1, 1.0);  // y(M-1)
+        const double y_hi = fmadd(-Q1, y_lo, E1);                      // y(M)
+        double yn = half ? y_hi : y_lo;
+        if (active && nsteps > 0)
+            IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, yn);
+#pragma unroll
+        for (int tt = KH - 2; tt >= 0; --tt) {
+            if (tt >= shift) {
+                yn = fmadd(-P[tt], yn, D[tt]);
+                if (active)
+                    IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(tt - shift)) * sk_bytes, yn);
+            }
+        }
     }
 }
 
@@ -582,7 +640,7 @@ template <class T, bool FUSED, int TJ, int PF, int KH, int WPE, bool NT, bool EX
 __global__ __launch_bounds__(128 * TJ) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void
 k_column(ColumnArgs p) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
-    column_tile<T, FUSED, false, TJ, PF, KH, NT, EXACT>(p, t % p.nbi, t / p.nbi, 0.0);
+    column_tile<T, FUSED, 0, TJ, PF, KH, NT, EXACT>(p, t % p.nbi, t / p.nbi, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -610,7 +668,7 @@ struct ColumnBatch {
     double kappa;
 };
 
-template <class T, bool VDIFF, int TJ, int PF, int KH, int WPE>
+template <class T, int VD, int TJ, int PF, int KH, int WPE>
 __global__ __launch_bounds__(128 * TJ) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void
 k_column_batch(ColumnBatch b) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -624,7 +682,7 @@ k_column_batch(ColumnBatch b) {
     a.x = sb.x[f];
     // Coefficients are shared by the fields of a subdomain (re-read through
     // L2): default policy; the output streams.
-    column_tile<T, true, VDIFF, TJ, PF, KH, false, false, true>(a, tile % a.nbi, tile / a.nbi, b.kappa);
+    column_tile<T, true, VD, TJ, PF, KH, false, false, true>(a, tile % a.nbi, tile / a.nbi, b.kappa);
 }
 
 // ---------------------------------------------------------------------------

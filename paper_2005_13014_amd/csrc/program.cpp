@@ -41,9 +41,9 @@ int check_halo(const stencil_field_t *f, const char *name, int need);
 size_t elem_size(int dtype);
 bool empty(const stencil_field_t *f);
 
-hipError_t launch_column_batch_f64(const ColumnBatch &, bool, int, int, int, int, hipStream_t);
-hipError_t launch_column_batch_f32(const ColumnBatch &, bool, int, int, int, int, hipStream_t);
-hipError_t launch_column_batch_bf16(const ColumnBatch &, bool, int, int, int, int, hipStream_t);
+hipError_t launch_column_batch_f64(const ColumnBatch &, int, int, int, int, int, hipStream_t);
+hipError_t launch_column_batch_f32(const ColumnBatch &, int, int, int, int, int, hipStream_t);
+hipError_t launch_column_batch_bf16(const ColumnBatch &, int, int, int, int, int, hipStream_t);
 hipError_t launch_hgrad_batch_f64(const HgradBatch &, int, hipStream_t);
 hipError_t launch_hgrad_batch_f32(const HgradBatch &, int, hipStream_t);
 hipError_t launch_hgrad_batch_bf16(const HgradBatch &, int, hipStream_t);
@@ -89,7 +89,8 @@ struct ColumnLaunch {
 // The planned program: everything a replay needs, pointers included.
 struct Plan {
     int dtype = 0;
-    bool vdiff = false, hgrad = false;
+    int vdiff = 0;  // 0 none, 1 explicit, 2 implicit vertical diffusion
+    bool hgrad = false;
     std::vector<ColumnLaunch> col;
     std::vector<HgradBatch> hg;
     std::vector<int> hg_tiles;
@@ -140,10 +141,10 @@ int check_program(const stencil_program_t *prog, int *dtype_out) {
     if (prog->nsub > 0 && !prog->sub) return fail(STENCIL_E_NULL, "program subdomains are NULL");
     const int st = prog->stages;
     const int chain1 = STENCIL_STAGE_HDIFF | STENCIL_STAGE_VADV;
-    const int chain2 = chain1 | STENCIL_STAGE_VDIFF;
-    const int chain3 = chain2 | STENCIL_STAGE_HGRAD;
-    if (st != chain1 && st != chain2 && st != chain3)
-        return fail(STENCIL_E_ARG, "stages must be HDIFF|VADV[|VDIFF[|HGRAD]] (got %d)", st);
+    const int chain2 = chain1 | STENCIL_STAGE_VDIFF, chain2i = chain1 | STENCIL_STAGE_VDIFF_IMPLICIT;
+    const int chain3 = chain2 | STENCIL_STAGE_HGRAD, chain3i = chain2i | STENCIL_STAGE_HGRAD;
+    if (st != chain1 && st != chain2 && st != chain3 && st != chain2i && st != chain3i)
+        return fail(STENCIL_E_ARG, "stages must be HDIFF|VADV[|VDIFF or VDIFF_IMPLICIT[|HGRAD]] (got %d)", st);
     if (prog->flags & ~(STENCIL_PROGRAM_GRAPH | STENCIL_PROGRAM_AUTOTUNE))
         return fail(STENCIL_E_ARG, "unknown program flags %d", prog->flags);
     if (!std::isfinite(prog->dt) || !std::isfinite(prog->kappa) || !std::isfinite(prog->beta_h) ||
@@ -234,7 +235,7 @@ ColumnArgs column_args_ext(const stencil_field_t &cf, const stencil_subdomain_t 
 // offsets for y are laid out when `scratch` is null (sizing pass).
 int build_plan(const stencil_program_t *prog, int dtype, int tj, char *scratch, Plan *plan) {
     plan->dtype = dtype;
-    plan->vdiff = (prog->stages & STENCIL_STAGE_VDIFF) != 0;
+    plan->vdiff = (prog->stages & STENCIL_STAGE_VDIFF_IMPLICIT) ? 2 : (prog->stages & STENCIL_STAGE_VDIFF) ? 1 : 0;
     plan->hgrad = (prog->stages & STENCIL_STAGE_HGRAD) != 0;
     plan->col.clear();
     plan->hg.clear();

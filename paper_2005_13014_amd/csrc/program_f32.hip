@@ -4,13 +4,13 @@
 
 namespace stl {
 
-template <bool VDIFF, int TJ, int PF>
+template <int VD, int TJ, int PF>
 static hipError_t by_levels(const ColumnBatch &b, int kh, int ntiles, hipStream_t st) {
     switch (kh) {
-    case 16: return launch_column_batch_t<float, VDIFF, TJ, PF, 16, 2>(b, ntiles, st);
-    case 32: return launch_column_batch_t<float, VDIFF, TJ, PF, 32, 2>(b, ntiles, st);
-    case 40: return launch_column_batch_t<float, VDIFF, TJ, PF, 40, 2>(b, ntiles, st);
-    case 48: return launch_column_batch_t<float, VDIFF, TJ, PF, 48, 1>(b, ntiles, st);
+    case 16: return launch_column_batch_t<float, VD, TJ, PF, 16, 2>(b, ntiles, st);
+    case 32: return launch_column_batch_t<float, VD, TJ, PF, 32, 2>(b, ntiles, st);
+    case 40: return launch_column_batch_t<float, VD, TJ, PF, 40, 2>(b, ntiles, st);
+    case 48: return launch_column_batch_t<float, VD, TJ, PF, 48, 1>(b, ntiles, st);
     }
     return hipErrorInvalidValue;
 }
@@ -21,14 +21,16 @@ bool batch_variant_f32(int tile_j, int prefetch) {
     return false;
 }
 
-hipError_t launch_column_batch_f32(const ColumnBatch &b, bool vdiff, int kh, int tile_j,
+hipError_t launch_column_batch_f32(const ColumnBatch &b, int vd, int kh, int tile_j,
                                    int prefetch, int ntiles, hipStream_t st) {
     if (tile_j == 2 && prefetch == 4)
-        return vdiff ? by_levels<true, 2, 4>(b, kh, ntiles, st)
-                     : by_levels<false, 2, 4>(b, kh, ntiles, st);
+        return vd == 2   ? by_levels<2, 2, 4>(b, kh, ntiles, st)
+               : vd == 1 ? by_levels<1, 2, 4>(b, kh, ntiles, st)
+                         : by_levels<0, 2, 4>(b, kh, ntiles, st);
     if (tile_j == 4 && prefetch == 4)
-        return vdiff ? by_levels<true, 4, 4>(b, kh, ntiles, st)
-                     : by_levels<false, 4, 4>(b, kh, ntiles, st);
+        return vd == 2   ? by_levels<2, 4, 4>(b, kh, ntiles, st)
+               : vd == 1 ? by_levels<1, 4, 4>(b, kh, ntiles, st)
+                         : by_levels<0, 4, 4>(b, kh, ntiles, st);
     return hipErrorInvalidValue;
 }
 

@@ -4,13 +4,13 @@
 
 namespace stl {
 
-template <bool VDIFF, int TJ, int PF>
+template <int VD, int TJ, int PF>
 static hipError_t by_levels(const ColumnBatch &b, int kh, int ntiles, hipStream_t st) {
     switch (kh) {
-    case 16: return launch_column_batch_t<double, VDIFF, TJ, PF, 16, 2>(b, ntiles, st);
-    case 32: return launch_column_batch_t<double, VDIFF, TJ, PF, 32, 1>(b, ntiles, st);
-    case 40: return launch_column_batch_t<double, VDIFF, TJ, PF, 40, 1>(b, ntiles, st);
-    case 48: return launch_column_batch_t<double, VDIFF, TJ, PF, 48, 1>(b, ntiles, st);
+    case 16: return launch_column_batch_t<double, VD, TJ, PF, 16, 2>(b, ntiles, st);
+    case 32: return launch_column_batch_t<double, VD, TJ, PF, 32, 1>(b, ntiles, st);
+    case 40: return launch_column_batch_t<double, VD, TJ, PF, 40, 1>(b, ntiles, st);
+    case 48: return launch_column_batch_t<double, VD, TJ, PF, 48, 1>(b, ntiles, st);
     }
     return hipErrorInvalidValue;
 }
@@ -20,11 +20,12 @@ bool batch_variant_f64(int tile_j, int prefetch) {
     return false;
 }
 
-hipError_t launch_column_batch_f64(const ColumnBatch &b, bool vdiff, int kh, int tile_j,
+hipError_t launch_column_batch_f64(const ColumnBatch &b, int vd, int kh, int tile_j,
                                    int prefetch, int ntiles, hipStream_t st) {
     if (tile_j == 2 && prefetch == 2)
-        return vdiff ? by_levels<true, 2, 2>(b, kh, ntiles, st)
-                     : by_levels<false, 2, 2>(b, kh, ntiles, st);
+        return vd == 2   ? by_levels<2, 2, 2>(b, kh, ntiles, st)
+               : vd == 1 ? by_levels<1, 2, 2>(b, kh, ntiles, st)
+                         : by_levels<0, 2, 2>(b, kh, ntiles, st);
     return hipErrorInvalidValue;
 }
 

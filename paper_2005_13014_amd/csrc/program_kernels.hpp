@@ -111,9 +111,9 @@ __global__ __launch_bounds__(256) void k_hgrad_batch(HgradBatch b) {
     }
 }
 
-template <class T, bool VDIFF, int TJ, int PF, int KH, int WPE>
+template <class T, int VD, int TJ, int PF, int KH, int WPE>
 static hipError_t launch_column_batch_t(const ColumnBatch &b, int ntiles, hipStream_t st) {
-    hipLaunchKernelGGL((k_column_batch<T, VDIFF, TJ, PF, KH, WPE>), dim3(ntiles), dim3(128 * TJ), 0, st,
+    hipLaunchKernelGGL((k_column_batch<T, VD, TJ, PF, KH, WPE>), dim3(ntiles), dim3(128 * TJ), 0, st,
                        b);
     return hipGetLastError();
 }

@@ -247,6 +247,10 @@ def test_program_validation():
     assert B.lib().stencil_program_run(None, None) == 1
     p, keep = program(stages=1 | 4)
     assert run_program(p) == 9
+    p, keep = program(stages=1 | 2 | 4 | 16)           # explicit and implicit vdiff together
+    assert run_program(p) == 9
+    p, keep = program(stages=1 | 2 | 16 | 8, halo_u=2)  # implicit chain with hgrad: u needs 3
+    assert run_program(p) == 5
     p, keep = program(halo_u=2)                      # hgrad grows the domain: u needs 3
     assert run_program(p) == 5
     p, keep = program(halo_c=0)                      # coefficients need the 1-cell ring

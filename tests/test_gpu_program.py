@@ -18,6 +18,7 @@ from paper_2005_13014_amd import binding as B  # noqa: E402
 
 KAPPA, BH, BV = 0.1, 0.05, 0.01
 FULL = B.STAGE_HDIFF | B.STAGE_VADV | B.STAGE_VDIFF | B.STAGE_HGRAD
+FULL_IMPLICIT = B.STAGE_HDIFF | B.STAGE_VADV | B.STAGE_VDIFF_IMPLICIT | B.STAGE_HGRAD
 
 
 def note(*a):
@@ -39,11 +40,13 @@ def device_program(data, dtype, canary=-7.0):
 def reference(d, f, stages):
     h = d["halo"]
     args = (d["u"][f], h, d["coeff"], h, d["wcon"], h, d["a"], h, d["b"], h, d["c"], h, DT)
-    if stages == FULL:
-        return oracle.timestep(*args, KAPPA, BH, BV)
+    if stages in (FULL, FULL_IMPLICIT):
+        return oracle.timestep(*args, KAPPA, BH, BV, implicit=stages == FULL_IMPLICIT)
     x = oracle.hdiff_vadv(*args)
     if stages & B.STAGE_VDIFF:
         x = oracle.vdiff(x, 0, KAPPA)
+    if stages & B.STAGE_VDIFF_IMPLICIT:
+        x = oracle.vdiff_implicit(x, 0, KAPPA)
     return x
 
 
@@ -59,7 +62,9 @@ def small_data(dtype, nfields=3, shapes=((70, 13, 9), (40, 33, 17), (5, 3, 1), (
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("stages", [B.STAGE_HDIFF | B.STAGE_VADV,
-                                    B.STAGE_HDIFF | B.STAGE_VADV | B.STAGE_VDIFF, FULL])
+                                    B.STAGE_HDIFF | B.STAGE_VADV | B.STAGE_VDIFF, FULL,
+                                    B.STAGE_HDIFF | B.STAGE_VADV | B.STAGE_VDIFF_IMPLICIT,
+                                    FULL_IMPLICIT])
 def test_program_stage_chains(dtype, stages):
     data = small_data(dtype)
     subs = device_program(data, dtype)
@@ -90,6 +95,21 @@ def test_config4_six_subdomains_eight_fields():
             worst = max(worst, e)
     note("C4 worst normwise %.2e" % worst)
     assert worst <= TOL["f32"]
+
+
+def test_implicit_vertical_diffusion_six_subdomains():
+    """The timestep with the implicit vertical diffusion on the 6 uneven
+    subdomains (60 .. 90 levels, every register bucket), FP32 and FP64."""
+    for dtype in ("f64", "f32"):
+        data = inputs.batched(storage=dtype, nfields=2)
+        subs = device_program(data, dtype)
+        run(subs, FULL_IMPLICIT, flags=B.PROGRAM_AUTOTUNE)
+        worst = 0.0
+        for d, s in zip(data, subs):
+            for f in range(len(d["u"])):
+                worst = max(worst, normwise(s["z"][f].to_numpy(interior=True), reference(d, f, FULL_IMPLICIT)))
+        note("implicit timestep %s worst normwise %.2e" % (dtype, worst))
+        assert worst <= TOL[dtype]
 
 
 def test_graph_replays_match_eager():
