@@ -162,6 +162,26 @@ def read_probe():
     return nb / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
 
 
+def streams_probe(ni=512, nj=512, nk=80):
+    """HBM rate (GB/s) of the fused kernel's traffic mix at the headline size:
+    six field-sized arrays read and one written, streamed element by element."""
+    import torch
+    from paper_2005_13014_amd import binding as B
+    n = ni * nj * nk
+    srcs = [torch.empty(n, dtype=torch.float32, device="cuda").fill_(float(q)) for q in range(6)]
+    dst = torch.empty(n, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        B.stencil_probe_streams(srcs, dst, 4 * n)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        B.stencil_probe_streams(srcs, dst, 4 * n)
+    e1.record()
+    torch.cuda.synchronize()
+    return 7 * 4 * n / (e0.elapsed_time(e1) / 20 * 1e-3) / 1e9
+
+
 def variant_column(ni, nj, nk, dtype, level):
     """Fused (level 0) or unfused 'original' (level 1) program in dtype."""
     import torch
@@ -455,7 +475,7 @@ def main():
                 cal = json.load(fh)["fetch_calibration"]
         except (OSError, ValueError, KeyError):
             pass
-        for v in ("timestep", "adjoint"):
+        for v in ("timestep", "timestep_implicit", "adjoint"):
             import glob
             if glob.glob(os.path.join(args.summarize_profiles, "v_%s_trace" % v, "**", "*kernel_stats.csv"),
                          recursive=True):
@@ -520,7 +540,8 @@ def main():
     }
     if args.quick:
         if args.with_copy:
-            log("copy probe %.1f GB/s, read probe %.1f GB/s" % (copy_probe(), read_probe()))
+            log("copy probe %.1f GB/s, read probe %.1f GB/s, 6-in 1-out probe %.1f GB/s"
+                % (copy_probe(), read_probe(), streams_probe(ni, nj, nk)))
         print(json.dumps(result), flush=True)
         return
 
@@ -530,7 +551,8 @@ def main():
     result["error_vs_fp64_oracle"] = errors(sets[0][0], sets[0][1]["x"])
     del sets
     torch.cuda.empty_cache()
-    variants = {"copy_probe_GBs": copy_probe(), "read_probe_GBs": read_probe()}
+    variants = {"copy_probe_GBs": copy_probe(), "read_probe_GBs": read_probe(),
+                "streams_6in_1out_probe_GBs": streams_probe(ni, nj, nk)}
     torch.cuda.empty_cache()
     for label, dt_, level in (("fused_f64", "f64", 0), ("original_f64", "f64", 1),
                               ("fused_bf16", "bf16", 0)):

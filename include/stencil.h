@@ -254,6 +254,13 @@ int stencil_probe_copy(const void *src, void *dst, int64_t nbytes, void *stream)
  * HBM read rate. */
 int stencil_probe_read(const void *src, int64_t nbytes, uint32_t key, void *sink, void *stream);
 
+/* Bandwidth probe: reads nsrc (1 .. 8) arrays of nbytes each (a multiple of
+ * 16, pointers 16-byte aligned) and writes their element-wise XOR to dst
+ * (nbytes, not overlapping any source), all streamed non-temporally.  With
+ * six sources it has the traffic mix of the fused kernel: six field streams
+ * in, one out. */
+int stencil_probe_streams(const void *const *src, int32_t nsrc, void *dst, int64_t nbytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,7 @@ _SIGNATURES = {
     "stencil_shutdown": [],
     "stencil_probe_copy": [_V, _V, ctypes.c_int64, _V],
     "stencil_probe_read": [_V, ctypes.c_int64, ctypes.c_uint32, _V, _V],
+    "stencil_probe_streams": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, _V, ctypes.c_int64, _V],
 }
 EXPORTS = tuple(_SIGNATURES)
 
@@ -275,6 +276,12 @@ def stencil_probe_copy(src, dst, nbytes, stream=None):
 def stencil_probe_read(src, nbytes, key, sink, stream=None):
     _check(lib().stencil_probe_read(ctypes.c_void_p(src.data_ptr()), int(nbytes), int(key),
                                     ctypes.c_void_p(sink.data_ptr()), _stream(stream)))
+
+
+def stencil_probe_streams(srcs, dst, nbytes, stream=None):
+    arr = (ctypes.c_void_p * len(srcs))(*[t.data_ptr() for t in srcs])
+    _check(lib().stencil_probe_streams(arr, len(srcs), ctypes.c_void_p(dst.data_ptr()), int(nbytes),
+                                       _stream(stream)))
 
 
 def stencil_last_error():

@@ -514,6 +514,23 @@ STENCIL_API int stencil_probe_copy(const void *src, void *dst, int64_t nbytes, v
                          "copy kernel");
 }
 
+STENCIL_API int stencil_probe_streams(const void *const *src, int32_t nsrc, void *dst, int64_t nbytes,
+                                      void *stream) {
+    if (!src || !dst) return fail(STENCIL_E_NULL, "probe_streams: NULL pointer");
+    if (nsrc < 1 || nsrc > 8) return fail(STENCIL_E_ARG, "probe_streams: nsrc must be 1 .. 8 (got %d)", nsrc);
+    if (nbytes < 0 || nbytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+        return fail(STENCIL_E_ARG, "probe_streams: nbytes and pointers must be 16-byte aligned");
+    const uintptr_t d = reinterpret_cast<uintptr_t>(dst);
+    for (int f = 0; f < nsrc; ++f) {
+        if (!src[f]) return fail(STENCIL_E_NULL, "probe_streams: source %d is NULL", f);
+        const uintptr_t s = reinterpret_cast<uintptr_t>(src[f]);
+        if (s % 16) return fail(STENCIL_E_ARG, "probe_streams: nbytes and pointers must be 16-byte aligned");
+        if (s < d + nbytes && d < s + nbytes) return fail(STENCIL_E_ALIAS, "probe_streams: source %d overlaps dst", f);
+    }
+    return launch_status(launch_probe_streams(src, nsrc, dst, nbytes, static_cast<hipStream_t>(stream)),
+                         "streams kernel");
+}
+
 STENCIL_API int stencil_probe_read(const void *src, int64_t nbytes, uint32_t key, void *sink, void *stream) {
     if (!src || !sink) return fail(STENCIL_E_NULL, "probe_read: NULL pointer");
     if (nbytes < 0 || nbytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 ||

@@ -67,5 +67,6 @@ hipError_t launch_adjoint(int dtype, const AdjointArgs &a, void *scratch, hipStr
 // Streaming copy used as the bandwidth probe (probe.hip).
 hipError_t launch_probe_copy(const void *src, void *dst, long long nbytes, hipStream_t st);
 hipError_t launch_probe_read(const void *src, long long nbytes, unsigned key, void *sink, hipStream_t st);
+hipError_t launch_probe_streams(const void *const *src, int nsrc, void *dst, long long nbytes, hipStream_t st);
 
 }  // namespace stl

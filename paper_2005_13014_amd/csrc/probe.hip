@@ -48,6 +48,49 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_read16(const uint4 *__restrict_
     if (acc == key) sink[0] = acc;
 }
 
+// Multi-stream probe: nsrc arrays read and one written, 16 bytes per lane
+// per array (the traffic mix of the fused kernel: six field streams in, one
+// out, the output stored non-temporally as the fused kernel stores it).
+constexpr int PROBE_MAX_STREAMS = 8;
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+struct StreamArgs {
+    const uint4 *src[PROBE_MAX_STREAMS];
+    uint4 *dst;
+    int nsrc;
+    long long n;  // 16-byte vectors per stream
+};
+
+__global__ __launch_bounds__(PROBE_BLOCK) void k_streams(StreamArgs a) {
+    const long long stride = static_cast<long long>(gridDim.x) * PROBE_BLOCK * PROBE_UNROLL;
+    for (long long base = static_cast<long long>(blockIdx.x) * PROBE_BLOCK * PROBE_UNROLL + threadIdx.x;
+         base < a.n; base += stride) {
+        uint4 acc[PROBE_UNROLL] = {};
+        for (int f = 0; f < a.nsrc; ++f) {
+            uint4 v[PROBE_UNROLL];
+#pragma unroll
+            for (int u = 0; u < PROBE_UNROLL; ++u) {
+                const long long q = base + static_cast<long long>(u) * PROBE_BLOCK;
+                v[u] = q < a.n ? a.src[f][q] : uint4{};
+            }
+#pragma unroll
+            for (int u = 0; u < PROBE_UNROLL; ++u) {
+                acc[u].x ^= v[u].x;
+                acc[u].y ^= v[u].y;
+                acc[u].z ^= v[u].z;
+                acc[u].w ^= v[u].w;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) {
+            const long long q = base + static_cast<long long>(u) * PROBE_BLOCK;
+            if (q < a.n) {
+                const u32x4 w = {acc[u].x, acc[u].y, acc[u].z, acc[u].w};
+                __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(a.dst + q));
+            }
+        }
+    }
+}
+
 static unsigned probe_blocks(long long n, long long cap) {
     long long blocks = (n + PROBE_BLOCK * PROBE_UNROLL - 1) / (PROBE_BLOCK * PROBE_UNROLL);
     return static_cast<unsigned>(blocks < cap ? blocks : cap);
@@ -68,6 +111,18 @@ hipError_t launch_probe_read(const void *src, long long nbytes, unsigned key, vo
     // 8 workgroups per CU (the best measured grid for reads), grid-stride beyond.
     hipLaunchKernelGGL(k_read16, dim3(probe_blocks(n, 256 * 8)), dim3(PROBE_BLOCK), 0, st,
                        static_cast<const uint4 *>(src), n, key, static_cast<unsigned *>(sink));
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_streams(const void *const *src, int nsrc, void *dst, long long nbytes, hipStream_t st) {
+    if (nsrc < 1 || nsrc > PROBE_MAX_STREAMS) return hipErrorInvalidValue;
+    StreamArgs a{};
+    for (int f = 0; f < nsrc; ++f) a.src[f] = static_cast<const uint4 *>(src[f]);
+    a.dst = static_cast<uint4 *>(dst);
+    a.nsrc = nsrc;
+    a.n = nbytes / 16;
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_streams, dim3(probe_blocks(a.n, 256 * 16)), dim3(PROBE_BLOCK), 0, st, a);
     return hipGetLastError();
 }
 

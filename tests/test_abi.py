@@ -208,6 +208,13 @@ def test_probe_copy_validation():
     assert lib.stencil_probe_copy(None, ctypes.c_void_p(FAKE), 16, None) == 1
     assert lib.stencil_probe_copy(ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE + 1024), 17, None) == 9
     assert lib.stencil_probe_copy(ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE + 16), 64, None) == 6
+    V = ctypes.c_void_p
+    srcs = (V * 2)(FAKE, FAKE + (1 << 20))
+    assert lib.stencil_probe_streams(srcs, 0, V(FAKE + (2 << 20)), 64, None) == 9
+    assert lib.stencil_probe_streams(srcs, 9, V(FAKE + (2 << 20)), 64, None) == 9
+    assert lib.stencil_probe_streams(srcs, 2, V(FAKE + 32), 64, None) == 6
+    assert lib.stencil_probe_streams(srcs, 2, None, 64, None) == 1
+    assert lib.stencil_probe_streams(srcs, 2, V(FAKE + (2 << 20)), 24, None) == 9
     assert lib.stencil_probe_read(None, 16, 0, ctypes.c_void_p(FAKE), None) == 1
     assert lib.stencil_probe_read(ctypes.c_void_p(FAKE), 16, 0, None, None) == 1
     assert lib.stencil_probe_read(ctypes.c_void_p(FAKE), 24, 0, ctypes.c_void_p(FAKE), None) == 9

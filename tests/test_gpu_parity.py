@@ -266,6 +266,18 @@ def test_probe_copy():
     assert torch.equal(dst2[:m], src[:m]) and not dst2[m:].any()
 
 
+def test_probe_streams():
+    n = (1 << 20) + 12  # ragged: not a multiple of the 4096-vector trip
+    srcs = [torch.randint(-2**31, 2**31 - 1, (n,), dtype=torch.int32, device="cuda") for _ in range(6)]
+    dst = torch.zeros(n + 4, dtype=torch.int32, device="cuda")
+    B.stencil_probe_streams(srcs, dst, n * 4)
+    torch.cuda.synchronize()
+    ref = srcs[0]
+    for t in srcs[1:]:
+        ref = torch.bitwise_xor(ref, t)
+    assert torch.equal(dst[:n], ref) and not dst[n:].any()
+
+
 def test_probe_read():
     n = 1 << 22
     src = torch.ones(n, dtype=torch.int32, device="cuda")
