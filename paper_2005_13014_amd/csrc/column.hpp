@@ -48,10 +48,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
 template <class T> struct BufIO;
 
 // Cache policy operand of the buffer intrinsics: 0 = default, 2 = non-temporal.
+// load_raw returns the stored bits in a register of type R and cvt widens
+// them to the compute type; a prefetch ring holds raw values, so a load issued
+// in a conditional block needs no conversion (and no wait for its data) there.
 template <> struct BufIO<float> {
+    using R = float;
+    template <int CP = 0>
+    static __device__ __forceinline__ float load_raw(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, CP));
+    }
+    static __device__ __forceinline__ float cvt(float v) { return v; }
     template <int CP = 0>
     static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, CP));
+        return load_raw<CP>(r, vo, so);
     }
     template <int CP = 0>
     static __device__ __forceinline__ void store_d(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
@@ -61,9 +70,15 @@ template <> struct BufIO<float> {
 };
 
 template <> struct BufIO<double> {
+    using R = double;
+    template <int CP = 0>
+    static __device__ __forceinline__ double load_raw(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, CP));
+    }
+    static __device__ __forceinline__ double cvt(double v) { return v; }
     template <int CP = 0>
     static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, CP));
+        return load_raw<CP>(r, vo, so);
     }
     template <int CP = 0>
     static __device__ __forceinline__ void store_d(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
@@ -74,17 +89,20 @@ template <> struct BufIO<double> {
 };
 
 template <> struct BufIO<uint16_t> {
+    using R = uint32_t;  // the 16 stored bits, zero-extended
+    template <int CP = 0>
+    static __device__ __forceinline__ uint32_t load_raw(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, CP);
+    }
+    static __device__ __forceinline__ float cvt(uint32_t b) { return __uint_as_float(b << 16); }
     template <int CP = 0>
     static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-        const uint32_t b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, CP);
-        return __uint_as_float(b << 16);
+        return cvt(load_raw<CP>(r, vo, so));
     }
     template <int CP = 0>
     static __device__ __forceinline__ void store_d(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                                    double v) {
-        uint16_t b;
-        Storage<uint16_t>::store_d(&b, v);
-        __builtin_amdgcn_raw_buffer_store_b16(b, r, vo, so, CP);
+        __builtin_amdgcn_raw_buffer_store_b16(Storage<uint16_t>::round_d(v), r, vo, so, CP);
     }
 };
 
@@ -190,21 +208,22 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     const int shift = EXACT ? 0 : KH - nsteps;
     auto level = [&](int t) { return half ? (EXACT ? 2 * KH : K) - 1 - t : t; };
 
-    C rum[PF][FUSED ? MR : 1], rus[PF], rcfv[PF], rwv[PF], rlov[PF], rbv[PF], rupv[PF];
+    using R = typename IO::R;
+    R rum[PF][FUSED ? MR : 1], rus[PF], rcfv[PF], rwv[PF], rlov[PF], rbv[PF], rupv[PF];
     auto load = [&](int q, int s) {  // inputs of step s (padding steps re-read level 0)
         const uint32_t so = static_cast<uint32_t>(level(max(s - shift, 0))) * sk_bytes;
         if constexpr (FUSED) {
 #pragma unroll
-            for (int m = 0; m < MR; ++m) rum[q][m] = IO::load(ru, vmain[m], so);
-            if (side_wave) rus[q] = IO::load(ru, vside, so);
-            rcfv[q] = IO::template load<CP>(rcf, vcol, so);
+            for (int m = 0; m < MR; ++m) rum[q][m] = IO::load_raw(ru, vmain[m], so);
+            if (side_wave) rus[q] = IO::load_raw(ru, vside, so);
+            rcfv[q] = IO::template load_raw<CP>(rcf, vcol, so);
         } else {
-            rum[q][0] = IO::template load<CP>(ru, vcol, so);
+            rum[q][0] = IO::template load_raw<CP>(ru, vcol, so);
         }
-        rwv[q] = IO::template load<CP>(rw, vcol, so);
-        rlov[q] = IO::template load<CP>(rlo, vcol, so);
-        rbv[q] = IO::template load<CP>(rb, vcol, so);
-        rupv[q] = IO::template load<CP>(rup, vcol, so);
+        rwv[q] = IO::template load_raw<CP>(rw, vcol, so);
+        rlov[q] = IO::template load_raw<CP>(rlo, vcol, so);
+        rbv[q] = IO::template load_raw<CP>(rb, vcol, so);
+        rupv[q] = IO::template load_raw<CP>(rup, vcol, so);
     };
 #pragma unroll
     for (int q = 0; q < PF && q < KH; ++q) load(q, q);
@@ -223,14 +242,14 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
         C *tb = &tile[(half * 2 + (s & 1)) * TILE];
         if constexpr (FUSED) {
 #pragma unroll
-            for (int m = 0; m < MR; ++m) tb[lmain[m]] = rum[q][m];
-            if (side_wave) tb[lside] = rus[q];
+            for (int m = 0; m < MR; ++m) tb[lmain[m]] = IO::cvt(rum[q][m]);
+            if (side_wave) tb[lside] = IO::cvt(rus[q]);
         }
-        const C hv = FUSED ? C(0) : rum[q][0];
-        const C cf = FUSED ? rcfv[q] : C(0);
-        const C wv = rwv[q];
-        const double lov = static_cast<double>(rlov[q]), bv = static_cast<double>(rbv[q]),
-                     upv = static_cast<double>(rupv[q]);
+        const C hv = FUSED ? C(0) : IO::cvt(rum[q][0]);
+        const C cf = FUSED ? IO::cvt(rcfv[q]) : C(0);
+        const C wv = IO::cvt(rwv[q]);
+        const double lov = static_cast<double>(IO::cvt(rlov[q])), bv = static_cast<double>(IO::cvt(rbv[q])),
+                     upv = static_cast<double>(IO::cvt(rupv[q]));
         if (s + PF < KH) load(q, s + PF);
         if constexpr (FUSED) __syncthreads();
         const C h = FUSED ? hdiff_point<C, PI>(tb + (tj + 2) * PI + ti + 2, cf) : hv;
@@ -468,17 +487,18 @@ __device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int first,
     const int shift = EXACT ? 0 : KH - nsteps;  // leading identity rows, as in column_tile
     auto level = [&](int t) { return half ? (EXACT ? 2 * KH : K) - 1 - t : t; };
 
-    C rum[PF][MR], rus[PF], rcfv[PF], rwv[PF], rlov[PF], rbv[PF], rupv[PF];
+    using R = typename IO::R;  // raw ring values, widened where used
+    R rum[PF][MR], rus[PF], rcfv[PF], rwv[PF], rlov[PF], rbv[PF], rupv[PF];
     auto load = [&](int q, int s) {
         const uint32_t so = static_cast<uint32_t>(level(max(s - shift, 0))) * sk_bytes;
 #pragma unroll
-        for (int m = 0; m < MR; ++m) rum[q][m] = IO::load(ru, vmain[m], so);
-        if (side_wave) rus[q] = IO::load(ru, vside, so);
-        rcfv[q] = IO::template load<CP>(rcf, vcol, so);
-        rwv[q] = IO::template load<CP>(rw, vcol, so);
-        rlov[q] = IO::template load<CP>(rlo, vcol, so);
-        rbv[q] = IO::template load<CP>(rb, vcol, so);
-        rupv[q] = IO::template load<CP>(rup, vcol, so);
+        for (int m = 0; m < MR; ++m) rum[q][m] = IO::load_raw(ru, vmain[m], so);
+        if (side_wave) rus[q] = IO::load_raw(ru, vside, so);
+        rcfv[q] = IO::template load_raw<CP>(rcf, vcol, so);
+        rwv[q] = IO::template load_raw<CP>(rw, vcol, so);
+        rlov[q] = IO::template load_raw<CP>(rlo, vcol, so);
+        rbv[q] = IO::template load_raw<CP>(rb, vcol, so);
+        rupv[q] = IO::template load_raw<CP>(rup, vcol, so);
     };
     // Column values of the step whose hdiff comes next ("cur").
     C cf_c = C(0), w_c = C(0);
@@ -487,13 +507,13 @@ __device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int first,
         const int q = s % PF;
         C *tb = &tile[(half * 3 + s % 3) * TILE];
 #pragma unroll
-        for (int m = 0; m < MR; ++m) tb[lmain[m]] = rum[q][m];
-        if (side_wave) tb[lside] = rus[q];
-        cf_c = rcfv[q];
-        w_c = rwv[q];
-        lo_c = static_cast<double>(rlov[q]);
-        b_c = static_cast<double>(rbv[q]);
-        up_c = static_cast<double>(rupv[q]);
+        for (int m = 0; m < MR; ++m) tb[lmain[m]] = IO::cvt(rum[q][m]);
+        if (side_wave) tb[lside] = IO::cvt(rus[q]);
+        cf_c = IO::cvt(rcfv[q]);
+        w_c = IO::cvt(rwv[q]);
+        lo_c = static_cast<double>(IO::cvt(rlov[q]));
+        b_c = static_cast<double>(IO::cvt(rbv[q]));
+        up_c = static_cast<double>(IO::cvt(rupv[q]));
         if (s + PF < KH) load(q, s + PF);
     };
 

@@ -34,25 +34,26 @@ template <> struct Storage<uint16_t> {
     static __device__ __forceinline__ float load(const uint16_t *p) {
         return __uint_as_float(static_cast<uint32_t>(*p) << 16);
     }
-    static __device__ __forceinline__ uint16_t round(float v) {
-        uint32_t bits = __float_as_uint(v);
-        if ((bits & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((bits >> 16) | 0x40u);
-        bits += 0x7fffu + ((bits >> 16) & 1u);
-        return static_cast<uint16_t>(bits >> 16);
+    static __device__ __forceinline__ uint16_t round_bits(uint32_t bits) {
+        const uint32_t rne = (bits + 0x7fffu + ((bits >> 16) & 1u)) >> 16;
+        const uint32_t nan = (bits >> 16) | 0x40u;
+        return static_cast<uint16_t>((bits & 0x7fffffffu) > 0x7f800000u ? nan : rne);
     }
+    static __device__ __forceinline__ uint16_t round(float v) { return round_bits(__float_as_uint(v)); }
     static __device__ __forceinline__ void store(uint16_t *p, float v) { *p = round(v); }
     // A double rounded once to bfloat16: first to float with round-to-odd
     // (truncate, then set the last bit if anything was cut off), which keeps
     // the second rounding to nearest-even correct because float carries more
-    // than two extra bits.
-    static __device__ __forceinline__ void store_d(uint16_t *p, double v) {
-        float f = static_cast<float>(v);
-        // static_cast rounds to nearest; step back toward zero if it rounded up.
-        if (fabs(static_cast<double>(f)) > fabs(v)) f = nextafterf(f, 0.0f);
-        uint32_t bits = __float_as_uint(f);
-        if (static_cast<double>(f) != v) bits |= 1u;
-        *p = round(__uint_as_float(bits));
+    // than two extra bits.  Truncation steps the nearest float one unit
+    // toward zero when it rounded away (its bit pattern minus one: also right
+    // for an overflow to infinity); all selects, no branches.
+    static __device__ __forceinline__ uint16_t round_d(double v) {
+        const float f = static_cast<float>(v);
+        uint32_t bits = __float_as_uint(f) - (fabs(static_cast<double>(f)) > fabs(v) ? 1u : 0u);
+        bits |= static_cast<double>(__uint_as_float(bits)) != v ? 1u : 0u;
+        return round_bits(bits);
     }
+    static __device__ __forceinline__ void store_d(uint16_t *p, double v) { *p = round_d(v); }
 };
 
 // Resident workgroups of a kernel with `block` threads on the current device

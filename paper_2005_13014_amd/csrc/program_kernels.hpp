@@ -71,22 +71,24 @@ __global__ __launch_bounds__(256) void k_hgrad_batch(HgradBatch b) {
     const uint32_t skb = static_cast<uint32_t>(sb.sk) * ES;
 
     // Register ring rotated every level: (own0, two0) hold level k, (own1, two1) level k + 1.
-    C own0 = C(0), two0 = C(0), own1 = C(0), two1 = C(0);
-    auto load = [&](C &own, C &tw, int k) {
+    // Raw stored bits, widened where used.
+    using R = typename IO::R;
+    R own0 = R(0), two0 = R(0), own1 = R(0), two1 = R(0);
+    auto load = [&](R &own, R &tw, int k) {
         const uint32_t so = static_cast<uint32_t>(k) * skb;
-        own = IO::load(ry, v_own, so);
-        if (two) tw = IO::load(ry, v_two, so);
+        own = IO::load_raw(ry, v_own, so);
+        if (two) tw = IO::load_raw(ry, v_two, so);
     };
     load(own0, two0, 0);
     if (K > 1) load(own1, two1, 1);
 
     const C bh = static_cast<C>(b.beta_h), bv = static_cast<C>(b.beta_v), half = C(0.5);
-    C y_dn = C(0), y_c = own0;
+    C y_dn = C(0), y_c = IO::cvt(own0);
     for (int k = 0; k < K; ++k) {
         C *tb = &tile[(k & 1) * TILE];
-        tb[l_own] = own0;
-        if (two) tb[l_two] = two0;
-        const C y_up = k + 1 < K ? own1 : C(0);
+        tb[l_own] = IO::cvt(own0);
+        if (two) tb[l_two] = IO::cvt(two0);
+        const C y_up = k + 1 < K ? IO::cvt(own1) : C(0);
         // rotate: level k + 1 moves down, level k + 2 is requested
         own0 = own1;
         two0 = two1;
