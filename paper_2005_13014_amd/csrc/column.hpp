@@ -121,6 +121,121 @@ __device__ __forceinline__ double recip(double m) {
 __device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
 
 
+// Back-substitution of one column half, outward from the interface values
+// x_lo = x(M-1) and x_hi = x(M), and the vertical-diffusion epilogue VD: 0
+// stores x; 1 the explicit y = x + kappa (x(k+1) - 2 x(k) + x(k-1)); 2 the
+// implicit y - kappa (y(k+1) - 2 y(k) + y(k-1)) = x; both with zero flux
+// through the bottom and top faces.  Row tt of the elimination (P, D) is
+// local level tt - shift; level(t) maps a local level to k.  With VD = 2 every
+// thread of the workgroup must call it (it exchanges the interface rows of
+// the second solve through xch, partner slot xo).
+template <class T, int VD, int KH, int CPX, class Level>
+__device__ __forceinline__ void column_backsub(__amdgpu_buffer_rsrc_t rx, uint32_t vcol, uint32_t sk_bytes,
+                                               bool active, int half, int K, int M, int nsteps, int shift,
+                                               const Level &level, double (&P)[KH], double (&D)[KH],
+                                               double x_lo, double x_hi, double kappa, double2 *xch, int tid,
+                                               int xo) {
+#pragma clang fp contract(off)
+    using IO = BufIO<T>;
+    double xn = half ? x_hi : x_lo;
+    if constexpr (VD == 0) {
+        if (active && nsteps > 0)
+            IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, xn);
+#pragma unroll
+        for (int tt = KH - 2; tt >= 0; --tt) {
+            if (tt >= shift) {
+                xn = fmadd(-P[tt], xn, D[tt]);
+                if (active)
+                    IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(tt - shift)) * sk_bytes, xn);
+            }
+        }
+    } else if constexpr (VD == 1) {
+        // y at local level t + 1 is finished once x(t) is known: its neighbour
+        // toward the interface is x(t + 2) (the other half's interface value
+        // for t + 1 = nsteps - 1), away from it x(t).  Half 0 walks down
+        // (toward = up), half 1 walks up (toward = down).
+        const bool has_other = K > 1;
+        double x_in = half ? x_lo : x_hi;  // toward-interface neighbour of the current level
+        double x_cur = xn;
+        auto finish = [&](int t_loc, double toward, bool has_toward, double away, bool has_away) {
+            const double up = half ? away : toward, dn = half ? toward : away;
+            const bool has_up = half ? has_away : has_toward, has_dn = half ? has_toward : has_away;
+            const double g_up = has_up ? up - x_cur : 0.0;
+            const double g_dn = has_dn ? x_cur - dn : 0.0;
+            const double y = fmadd(kappa, g_up - g_dn, x_cur);
+            if (active) IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(t_loc)) * sk_bytes, y);
+        };
+#pragma unroll
+        for (int tt = KH - 2; tt >= 0; --tt) {
+            if (tt >= shift) {
+                const int t = tt - shift;
+                const double xt = fmadd(-P[tt], x_cur, D[tt]);
+                finish(t + 1, x_in, t + 1 < nsteps - 1 || has_other, xt, true);
+                x_in = x_cur;
+                x_cur = xt;
+            }
+        }
+        if (nsteps > 0) finish(0, x_in, nsteps > 1 || has_other, 0.0, false);
+    } else {
+        // Implicit vertical diffusion, y - kappa (G(k+1/2) - G(k-1/2)) = x with
+        // zero-flux end faces: a second, constant-coefficient tridiagonal
+        // solve over the same two-way split.  x(t) replaces D(t) as the walk
+        // produces it, then each half eliminates from its far end again
+        // (lower = the neighbour toward the far end, upper = toward the
+        // interface, both -kappa where they exist), the interface rows are
+        // solved as before and y is stored during the second walk outward.
+        D[KH - 1] = xn;
+#pragma unroll
+        for (int tt = KH - 2; tt >= 0; --tt)
+            if (tt >= shift) D[tt] = fmadd(-P[tt], D[tt + 1], D[tt]);
+        const bool toward_last = K - M > 0;  // the interface row has a neighbour across
+#pragma unroll
+        for (int st = 0; st < KH; ++st) {
+            const int t = st - shift;
+            const bool has_lo = t > 0, has_up = t < nsteps - 1 || toward_last;
+            double lo = has_lo ? -kappa : 0.0, up = has_up ? -kappa : 0.0;
+            double bd = 1.0 + (has_lo ? kappa : 0.0) + (has_up ? kappa : 0.0);
+            double xt = D[st];
+            if (t < 0) {  // padding row: identity with zero right-hand side
+                lo = 0.0;
+                up = 0.0;
+                bd = 1.0;
+                xt = 0.0;
+            }
+            if (st == 0) {
+                const double r = recip(bd);
+                P[0] = up * r;
+                D[0] = xt * r;
+            } else {
+                const int sm = st > 0 ? st - 1 : 0;
+                const double r = recip(fmadd(-lo, P[sm], bd));
+                P[st] = up * r;
+                D[st] = fmadd(-lo, D[sm], xt) * r;
+            }
+        }
+        const double Qm = nsteps > 0 ? P[KH - 1] : 0.0, Em = nsteps > 0 ? D[KH - 1] : 0.0;
+        __syncthreads();
+        xch[tid] = make_double2(Qm, Em);
+        __syncthreads();
+        const double2 o3 = xch[xo];
+        const double Q0 = half ? o3.x : Qm, E0 = half ? o3.y : Em;
+        const double Q1 = half ? Qm : o3.x, E1 = half ? Em : o3.y;
+        const double y_lo = fmadd(-Q0, E1, E0) / fmadd(-Q0, Q1, 1.0);  // y(M-1)
+        const double y_hi = fmadd(-Q1, y_lo, E1);                      // y(M)
+        double yn = half ? y_hi : y_lo;
+        if (active && nsteps > 0)
+            IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, yn);
+#pragma unroll
+        for (int tt = KH - 2; tt >= 0; --tt) {
+            if (tt >= shift) {
+                yn = fmadd(-P[tt], yn, D[tt]);
+                if (active)
+                    IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(tt - shift)) * sk_bytes, yn);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Workgroup = 2 halves x (64 x TJ lanes); the tile is 64 x TJ columns.
 // ---------------------------------------------------------------------------
@@ -315,106 +430,10 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     const double x_lo = fmadd(-P0, D1, D0) / fmadd(-P0, P1, 1.0);  // x(M-1)
     const double x_hi = fmadd(-P1, x_lo, D1);                      // x(M)
 
-    // Back-substitution outward from the interface.  Row tt of the
-    // elimination is local level tt - shift; the walk runs from the
-    // interface (local level nsteps - 1) down to local level 0.
-    double xn = half ? x_hi : x_lo;
-    if constexpr (VD == 0) {
-        if (active && nsteps > 0)
-            IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, xn);
-#pragma unroll
-        for (int tt = KH - 2; tt >= 0; --tt) {
-            if (tt >= shift) {
-                xn = fmadd(-P[tt], xn, D[tt]);
-                if (active)
-                    IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(tt - shift)) * sk_bytes, xn);
-            }
-        }
-    } else if constexpr (VD == 1) {
-        // y at local level t + 1 is finished once x(t) is known: its neighbour
-        // toward the interface is x(t + 2) (the other half's interface value
-        // for t + 1 = nsteps - 1), away from it x(t).  Half 0 walks down
-        // (toward = up), half 1 walks up (toward = down).
-        const bool has_other = K > 1;
-        double x_in = half ? x_lo : x_hi;  // toward-interface neighbour of the current level
-        double x_cur = xn;
-        auto finish = [&](int t_loc, double toward, bool has_toward, double away, bool has_away) {
-            const double up = half ? away : toward, dn = half ? toward : away;
-            const bool has_up = half ? has_away : has_toward, has_dn = half ? has_toward : has_away;
-            const double g_up = has_up ? up - x_cur : 0.0;
-            const double g_dn = has_dn ? x_cur - dn : 0.0;
-            const double y = fmadd(kappa, g_up - g_dn, x_cur);
-            if (active) IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(t_loc)) * sk_bytes, y);
-        };
-#pragma unroll
-        for (int tt = KH - 2; tt >= 0; --tt) {
-            if (tt >= shift) {
-                const int t = tt - shift;
-                const double xt = fmadd(-P[tt], x_cur, D[tt]);
-                finish(t + 1, x_in, t + 1 < nsteps - 1 || has_other, xt, true);
-                x_in = x_cur;
-                x_cur = xt;
-            }
-        }
-        if (nsteps > 0) finish(0, x_in, nsteps > 1 || has_other, 0.0, false);
-    } else {
-        // Implicit vertical diffusion, y - kappa (G(k+1/2) - G(k-1/2)) = x with
-        // zero-flux end faces: a second, constant-coefficient tridiagonal
-        // solve over the same two-way split.  x(t) replaces D(t) as the walk
-        // produces it, then each half eliminates from its far end again
-        // (lower = the neighbour toward the far end, upper = toward the
-        // interface, both -kappa where they exist), the interface rows are
-        // solved as before and y is stored during the second walk outward.
-        D[KH - 1] = xn;
-#pragma unroll
-        for (int tt = KH - 2; tt >= 0; --tt)
-            if (tt >= shift) D[tt] = fmadd(-P[tt], D[tt + 1], D[tt]);
-        const bool toward_last = K - M > 0;  // the interface row has a neighbour across
-#pragma unroll
-        for (int st = 0; st < KH; ++st) {
-            const int t = st - shift;
-            const bool has_lo = t > 0, has_up = t < nsteps - 1 || toward_last;
-            double lo = has_lo ? -kappa : 0.0, up = has_up ? -kappa : 0.0;
-            double bd = 1.0 + (has_lo ? kappa : 0.0) + (has_up ? kappa : 0.0);
-            double xt = D[st];
-            if (t < 0) {  // padding row: identity with zero right-hand side
-                lo = 0.0;
-                up = 0.0;
-                bd = 1.0;
-                xt = 0.0;
-            }
-            if (st == 0) {
-                const double r = recip(bd);
-                P[0] = up * r;
-                D[0] = xt * r;
-            } else {
-                const int sm = st > 0 ? st - 1 : 0;
-                const double r = recip(fmadd(-lo, P[sm], bd));
-                P[st] = up * r;
-                D[st] = fmadd(-lo, D[sm], xt) * r;
-            }
-        }
-        const double Qm = nsteps > 0 ? P[KH - 1] : 0.0, Em = nsteps > 0 ? D[KH - 1] : 0.0;
-        __syncthreads();
-        xch[tid] = make_double2(Qm, Em);
-        __syncthreads();
-        const double2 o3 = xch[half ? l : NH + l];
-        const double Q0 = half ? o3.x : Qm, E0 = half ? o3.y : Em;
-        const double Q1 = half ? Qm : o3.x, E1 = half ? Em : o3.y;
-        const double y_lo = fmadd(-Q0, E1, E0) / fmadd(-Q0, Q1, 1.0);  // y(M-1)
-        const double y_hi = fmadd(-Q1, y_lo, E1);                      // y(M)
-        double yn = half ? y_hi : y_lo;
-        if (active && nsteps > 0)
-            IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, yn);
-#pragma unroll
-        for (int tt = KH - 2; tt >= 0; --tt) {
-            if (tt >= shift) {
-                yn = fmadd(-P[tt], yn, D[tt]);
-                if (active)
-                    IO::template store_d<CPX>(rx, vcol, static_cast<uint32_t>(level(tt - shift)) * sk_bytes, yn);
-            }
-        }
-    }
+    // Back-substitution outward from the interface (local level nsteps - 1)
+    // down to local level 0.
+    column_backsub<T, VD, KH, CPX>(rx, vcol, sk_bytes, active, half, K, M, nsteps, shift, level, P, D, x_lo,
+                                   x_hi, kappa, xch, tid, half ? l : NH + l);
 }
 
 // Software-pipelined form of the fused tile (same arithmetic, same results).
@@ -616,16 +635,8 @@ __device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int first,
 #pragma unroll
             for (int q = 0; q < PF && q < KH; ++q) load(q, q);
         }
-        double xn = half ? x_hi : x_lo;
-        if (store && nsteps > 0)
-            IO::template store_d<CP>(rx, vx, static_cast<uint32_t>(level(nsteps - 1)) * sk_bytes, xn);
-#pragma unroll
-        for (int tt = KH - 2; tt >= 0; --tt) {
-            if (tt >= shift) {
-                xn = fmadd(-P[tt], xn, D[tt]);
-                if (store) IO::template store_d<CP>(rx, vx, static_cast<uint32_t>(level(tt - shift)) * sk_bytes, xn);
-            }
-        }
+        column_backsub<T, 0, KH, CP>(rx, vx, sk_bytes, store, half, K, M, nsteps, shift, level, P, D, x_lo, x_hi,
+                                     0.0, xch, tid, half ? l : NH + l);
         if (!more) break;
         t = tn;
     }
@@ -701,7 +712,8 @@ k_column_batch(ColumnBatch b) {
     a.u = sb.u[f];
     a.x = sb.x[f];
     // Coefficients are shared by the fields of a subdomain (re-read through
-    // L2): default policy; the output streams.
+    // L2): default policy; the output streams.  (The software-pipelined tile
+    // measured no faster here: the coefficient re-reads hit L2.)
     column_tile<T, true, VD, TJ, PF, KH, false, false, true>(a, tile % a.nbi, tile / a.nbi, b.kappa);
 }
 
