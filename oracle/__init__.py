@@ -270,6 +270,29 @@ def hdiff_vadv_adjoint(u, hu, coeff, hcf, w, hw, a, ha, b, hb, c, hc, dt, wl, hw
     return gu, gcoeff, gw
 
 
+def hdiff_vadv_jvp(u, hu, coeff, hcf, w, hw, a, ha, b, hb, c, hc, dt, du=None, hdu=2, dcoeff=None,
+                   hdcf=0, dw=None, hdw=0, da=None, db=None, dc=None, hdm=0, force_kx=None,
+                   force_ky=None):
+    """Forward mode: the tangent dx = J v of x = hdiff_vadv(...) in the
+    direction v = (du, dcoeff, dw, da, db, dc), each None for a zero tangent,
+    under the forward pass's limiter masks (or the forced ones).  du carries a
+    halo hdu >= 2, dcoeff / dw halos hdcf / hdw, da / db / dc the halo hdm.
+    Returns dx on the interior (halo 0)."""
+    lib = _load()
+    u, coeff, w, a, b, c = map(_f64, (u, coeff, w, a, b, c))
+    du, dcoeff, dw, da, db, dc = (None if t is None else _f64(t) for t in (du, dcoeff, dw, da, db, dc))
+    ni, nj, nk = _dims(u, hu)
+    dx = padded(ni, nj, nk, 0)
+    fkx = None if force_kx is None else np.ascontiguousarray(force_kx, dtype=np.uint8)
+    fky = None if force_ky is None else np.ascontiguousarray(force_ky, dtype=np.uint8)
+    rc = lib.oracle_hdiff_vadv_jvp(
+        _I(ni), _I(nj), _I(nk), _dp(u), _I(hu), _dp(coeff), _I(hcf), _dp(w), _I(hw), _dp(a), _I(ha),
+        _dp(b), _I(hb), _dp(c), _I(hc), _DBL(dt), _dp(du), _I(hdu), _dp(dcoeff), _I(hdcf), _dp(dw),
+        _I(hdw), _dp(da), _dp(db), _dp(dc), _I(hdm), _dp(dx), _I(0), _u8(fkx), _u8(fky))
+    _check(rc, "hdiff_vadv_jvp")
+    return dx
+
+
 def interior(a, h):
     """View of the interior of a padded array."""
     if h == 0:

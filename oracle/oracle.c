@@ -581,3 +581,112 @@ int oracle_hdiff_vadv_adjoint(int ni, int nj, int nk, const double *u, int hu,
     free(h); free(lam); free(gh); free(x);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Forward mode: the tangent of x = hdiff_vadv(u, coeff, w, a, b, c).       */
+/* ------------------------------------------------------------------------ */
+
+/* Tangent of the flux-form right-hand side: with F(k+1/2) = wf * hf (the two
+ * face averages), dF = (dw face average) * hf + wf * (dh face average), and
+ * dd(k) = dh(k) - dt * (dF(k+1/2) - dF(k-1/2)), zero tangent flux through the
+ * bottom and top faces.  dw may be NULL (zero).  All arrays on the interior. */
+static void rhs_tangent(int ni, int nj, int nk, const double *h, const double *dh, const double *w,
+                        int hw, const double *dw, int hdw, double dt, double *dd)
+{
+    for (int j = 0; j < nj; ++j)
+        for (int i = 0; i < ni; ++i)
+            for (int k = 0; k < nk; ++k) {
+                double df[2] = {0.0, 0.0}; /* below, above */
+                for (int s = 0; s < 2; ++s) {
+                    int k0 = s ? k : k - 1, k1 = k0 + 1;
+                    if (k0 < 0 || k1 >= nk) continue;
+                    double wf = 0.5 * (w[idx(ni, nj, hw, i, j, k0)] + w[idx(ni, nj, hw, i, j, k1)]);
+                    double hf = 0.5 * (h[idx(ni, nj, 0, i, j, k0)] + h[idx(ni, nj, 0, i, j, k1)]);
+                    double dwf = dw ? 0.5 * (dw[idx(ni, nj, hdw, i, j, k0)] + dw[idx(ni, nj, hdw, i, j, k1)])
+                                    : 0.0;
+                    double dhf = 0.5 * (dh[idx(ni, nj, 0, i, j, k0)] + dh[idx(ni, nj, 0, i, j, k1)]);
+                    df[s] = dwf * hf + wf * dhf;
+                }
+                dd[idx(ni, nj, 0, i, j, k)] = dh[idx(ni, nj, 0, i, j, k)] - dt * (df[1] - df[0]);
+            }
+}
+
+/* dx = J v for the direction v = (du, dcoeff, dw, da, db, dc); any of them
+ * may be NULL (a zero tangent).  The limiter masks are those of the forward
+ * pass (or force_kx / force_ky): the operator is piecewise linear in u on
+ * each side of a limiter switch, and the tangent is the derivative of the
+ * piece the forward pass took.  Stages, each the derivative of its forward
+ * counterpart:
+ *   dlap = lap(du); dflx = kept ? dlap(i+1) - dlap(i) : 0 (dfly likewise);
+ *   dh = du - dcoeff * div - coeff * ddiv, div and ddiv the flux divergences;
+ *   dd = tangent of the right-hand side (rhs_tangent);
+ *   T dx = dd - (da x(k-1) + db x(k) + dc x(k+1)), x the forward solution,
+ * the last because T x = d gives dT x + T dx = dd.  du needs halo 2 like u;
+ * dx is written on the interior with halo hdx. */
+int oracle_hdiff_vadv_jvp(int ni, int nj, int nk, const double *u, int hu, const double *coeff,
+                          int hcf, const double *w, int hw, const double *a, int ha, const double *b,
+                          int hb, const double *c, int hc, double dt, const double *du, int hdu,
+                          const double *dcoeff, int hdcf, const double *dw, int hdw, const double *da,
+                          const double *db, const double *dc, int hdm, double *dx, int hdx,
+                          const unsigned char *force_kx, const unsigned char *force_ky)
+{
+    if (bad_dims(ni, nj, nk) || hu < 2 || hcf < 0 || hw < 0 || ha < 0 || hb < 0 || hc < 0 ||
+        (du && hdu < 2) || hdcf < 0 || hdw < 0 || hdm < 0 || hdx < 0)
+        return ERR_ARG;
+    size_t n = padded_size(ni, nj, nk, 0), n1 = padded_size(ni, nj, nk, 1);
+    double *h = (double *)malloc((n + 1) * sizeof(double));
+    double *x = (double *)malloc((n + 1) * sizeof(double));
+    double *dh = (double *)calloc(n + 1, sizeof(double));
+    double *dd = (double *)malloc((n + 1) * sizeof(double));
+    double *flx = (double *)calloc(n1 + 1, sizeof(double));
+    double *fly = (double *)calloc(n1 + 1, sizeof(double));
+    double *dlap = (double *)calloc(n1 + 1, sizeof(double));
+    double *dflx = (double *)calloc(n1 + 1, sizeof(double));
+    double *dfly = (double *)calloc(n1 + 1, sizeof(double));
+    unsigned char *kx = (unsigned char *)calloc(n1 + 1, 1);
+    unsigned char *ky = (unsigned char *)calloc(n1 + 1, 1);
+    int rc = OK;
+    if (!h || !x || !dh || !dd || !flx || !fly || !dlap || !dflx || !dfly || !kx || !ky) rc = ERR_MEM;
+    /* Forward pass: h with its limited fluxes and keep masks, then x. */
+    if (rc == OK)
+        rc = oracle_hdiff_ex(ni, nj, nk, u, hu, coeff, hcf, h, 0, 0, flx, fly, kx, ky, force_kx,
+                             force_ky);
+    if (rc == OK) rc = oracle_vadv(ni, nj, nk, h, 0, w, hw, a, ha, b, hb, c, hc, dt, x, 0, 0);
+    /* Tangent of hdiff under the forward masks. */
+    if (rc == OK && du) {
+        rc = oracle_lap(ni, nj, nk, du, hdu, dlap, 1, 1);
+        if (rc == OK) {
+            flux_i(ni, nj, nk, du, hdu, dlap, 1, dflx, 1, NULL, kx, 0);
+            flux_j(ni, nj, nk, du, hdu, dlap, 1, dfly, 1, NULL, ky, 0);
+        }
+    }
+    for (int k = 0; rc == OK && k < nk; ++k)
+        for (int j = 0; j < nj; ++j)
+            for (int i = 0; i < ni; ++i) {
+                double div = flx[idx(ni, nj, 1, i, j, k)] - flx[idx(ni, nj, 1, i - 1, j, k)]
+                             + fly[idx(ni, nj, 1, i, j, k)] - fly[idx(ni, nj, 1, i, j - 1, k)];
+                double ddiv = dflx[idx(ni, nj, 1, i, j, k)] - dflx[idx(ni, nj, 1, i - 1, j, k)]
+                              + dfly[idx(ni, nj, 1, i, j, k)] - dfly[idx(ni, nj, 1, i, j - 1, k)];
+                double v = du ? du[idx(ni, nj, hdu, i, j, k)] : 0.0;
+                if (dcoeff) v -= dcoeff[idx(ni, nj, hdcf, i, j, k)] * div;
+                v -= coeff[idx(ni, nj, hcf, i, j, k)] * ddiv;
+                dh[idx(ni, nj, 0, i, j, k)] = v;
+            }
+    /* Tangent of the right-hand side, minus the matrix tangent applied to x. */
+    if (rc == OK) {
+        rhs_tangent(ni, nj, nk, h, dh, w, hw, dw, hdw, dt, dd);
+        for (int k = 0; k < nk; ++k)
+            for (int j = 0; j < nj; ++j)
+                for (int i = 0; i < ni; ++i) {
+                    double r = dd[idx(ni, nj, 0, i, j, k)];
+                    if (da && k > 0) r -= da[idx(ni, nj, hdm, i, j, k)] * x[idx(ni, nj, 0, i, j, k - 1)];
+                    if (db) r -= db[idx(ni, nj, hdm, i, j, k)] * x[idx(ni, nj, 0, i, j, k)];
+                    if (dc && k + 1 < nk) r -= dc[idx(ni, nj, hdm, i, j, k)] * x[idx(ni, nj, 0, i, j, k + 1)];
+                    dd[idx(ni, nj, 0, i, j, k)] = r;
+                }
+        rc = oracle_thomas(ni, nj, nk, a, ha, b, hb, c, hc, dd, 0, dx, hdx, 0);
+    }
+    free(h); free(x); free(dh); free(dd); free(flx); free(fly); free(dlap); free(dflx); free(dfly);
+    free(kx); free(ky);
+    return rc;
+}
