@@ -271,6 +271,36 @@ def variant_adjoint(n=256, nk=80):
     return out
 
 
+def variant_jvp(n=256, nk=80):
+    """Forward mode (tangent in all six inputs) at the reverse mode's size."""
+    import numpy as np
+    from paper_2005_13014_amd import binding as B
+    from paper_2005_13014_amd import inputs
+    out = {}
+    names = ("u", "coeff", "wcon", "a", "b", "c")
+    for dtype in ("f32", "f64"):
+        f = inputs.fields(n, n, nk, 2, seed=SEED + 6, storage=dtype)
+        rng = np.random.default_rng(SEED + 7)
+        g = {k: B.Field.from_numpy(f[k], 2, dtype) for k in names}
+        t = {k: B.Field.from_numpy(inputs.round_to(rng.standard_normal(f[k].shape), dtype), 2, dtype)
+             for k in names}
+        x = g["u"].like(fill=0.0)
+        B.stencil_hdiff_vadv(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT, x)
+        dx = g["u"].like(fill=0.0)
+
+        def fn(_):
+            B.stencil_hdiff_vadv_jvp(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT, dx, x=x,
+                                     du=t["u"], dcoeff=t["coeff"], dwcon=t["wcon"], da=t["a"], db=t["b"],
+                                     dc=t["c"])
+        w, k = time_calls(fn, [None], 20, 3)
+        es = ES[dtype]
+        # 13 streams in (u, du with their ring; 11 column fields incl. x), 1 out
+        ab = es * (2 * u_cells(n, n, nk) + 12 * n * n * nk)
+        out[dtype] = {"ms": w, "Gpoints_s": n * n * nk / (w * 1e-3) / 1e9,
+                      "algorithmic_GBs": ab / (k * 1e-3) / 1e9}
+    return out
+
+
 def cpu_baseline(ni, nj, nk, budget_s=10.0):
     import oracle
     from paper_2005_13014_amd import inputs
@@ -461,7 +491,7 @@ def main():
                     help="only the headline measurement (no variants, no CPU baseline)")
     ap.add_argument("--with-copy", action="store_true",
                     help="with --quick: also run the copy probe (counter calibration)")
-    ap.add_argument("--only", choices=["timestep", "timestep_implicit", "adjoint"],
+    ap.add_argument("--only", choices=["timestep", "timestep_implicit", "adjoint", "jvp"],
                     help="run only this variant and print its figures (for profiling)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write the profile summaries under profiles/ from rocprofv3 output in DIR "
@@ -475,7 +505,7 @@ def main():
                 cal = json.load(fh)["fetch_calibration"]
         except (OSError, ValueError, KeyError):
             pass
-        for v in ("timestep", "timestep_implicit", "adjoint"):
+        for v in ("timestep", "timestep_implicit", "adjoint", "jvp"):
             import glob
             if glob.glob(os.path.join(args.summarize_profiles, "v_%s_trace" % v, "**", "*kernel_stats.csv"),
                          recursive=True):
@@ -493,7 +523,7 @@ def main():
     log("device:", dev.name, "CUs:", dev.multi_processor_count)
     if args.only:
         fn = {"timestep": variant_program, "timestep_implicit": lambda: variant_program(implicit=True),
-              "adjoint": variant_adjoint}[args.only]
+              "adjoint": variant_adjoint, "jvp": variant_jvp}[args.only]
         print(json.dumps({"variant": args.only, "result": fn()}), flush=True)
         return
 
@@ -571,6 +601,9 @@ def main():
     torch.cuda.empty_cache()
     log("variant adjoint 256x256x80")
     variants["adjoint_256x256x80"] = variant_adjoint()
+    torch.cuda.empty_cache()
+    log("variant forward mode 256x256x80")
+    variants["jvp_256x256x80"] = variant_jvp()
     result["variants"] = variants
     log("cpu baseline (oracle)")
     result["cpu_baseline"] = cpu_baseline(ni, nj, nk)

@@ -177,6 +177,30 @@ int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stencil_field_t *
                                const stencil_field_t *gb, const stencil_field_t *gc,
                                const stencil_config_t *cfg, void *stream);
 
+/* Forward mode of stencil_hdiff_vadv: the tangent dx = J v in the direction
+ * v = (du, dcoeff, dwcon, da, db, dc), with the limiter decisions of the
+ * forward pass (a zeroed flux has a zero tangent):
+ *   dh = du - dcoeff * div - coeff * ddiv   (ddiv: div of the masked fluxes
+ *                                             of lap(du))
+ *   dF(k+1/2) = dwbar * hbar + wbar * dhbar, zero at the bottom and top
+ *   dd(k) = dh(k) - dt (dF(k+1/2) - dF(k-1/2))
+ *   T dx = dd - (da(k) x(k-1) + db(k) x(k) + dc(k) x(k+1))   (double)
+ * which follows from T x = d by differentiating every stage (Sec. V-A's
+ * inlining applied to the derivative: one fused kernel).
+ * Inputs: u (halo >= 2), coeff, wcon, a, b, c (interior read only); x, the
+ * forward result (interior; needed only when da, db or dc is given, else
+ * may be NULL); the tangents du (halo >= 2 when given), dcoeff, dwcon, da,
+ * db, dc (interior), each NULL for a zero tangent.  Output: dx (interior).
+ * nk <= 96 (STENCIL_E_UNSUPPORTED beyond).  cfg is unused (may be NULL). */
+int stencil_hdiff_vadv_jvp(const stencil_field_t *u, const stencil_field_t *coeff,
+                           const stencil_field_t *wcon, const stencil_field_t *a,
+                           const stencil_field_t *b, const stencil_field_t *c, double dt,
+                           const stencil_field_t *x, const stencil_field_t *du,
+                           const stencil_field_t *dcoeff, const stencil_field_t *dwcon,
+                           const stencil_field_t *da, const stencil_field_t *db,
+                           const stencil_field_t *dc, const stencil_field_t *dx,
+                           const stencil_config_t *cfg, void *stream);
+
 /* ---- batched timestep program ------------------------------------------ */
 
 /* Stages of a timestep program, applied in this order to every field. */

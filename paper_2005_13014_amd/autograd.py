@@ -9,6 +9,10 @@ adjoint (``stencil_hdiff_vadv_adjoint``) with the limiter decisions of the
 forward pass held fixed; the gradients of the matrix a, b, c (interior; the
 entries a(0) and c(K-1) outside the matrix get 0) come from the same
 transposed solve and the saved forward result.  No gradient flows to dt.
+
+Forward mode (``torch.autograd.forward_ad``) runs the hand-written tangent
+kernel (``stencil_hdiff_vadv_jvp``) under the same frozen limiter decisions;
+inputs without a tangent cost no loads.
 """
 from __future__ import annotations
 
@@ -36,11 +40,27 @@ class HdiffVadv(torch.autograd.Function):
         x = x_lay.like(fill=0.0)
         B.stencil_hdiff_vadv(u, coeff, wcon, a, b, c, dt, x)
         ctx.save_for_backward(u_buf, coeff_buf, wcon_buf, a_buf, b_buf, c_buf, x.buf)
+        ctx.save_for_forward(u_buf, coeff_buf, wcon_buf, a_buf, b_buf, c_buf, x.buf)
+        ctx.set_materialize_grads(False)  # absent tangents / gradients arrive as None
         ctx.meta = meta
         return x.buf
 
     @staticmethod
+    def jvp(ctx, du_buf, dcoeff_buf, dwcon_buf, da_buf, db_buf, dc_buf, _meta):
+        lay, dt = ctx.meta
+        u, coeff, wcon, a, b, c, x = (_wrap(t, lay) for t in ctx.saved_tensors)
+        tan = [None if t is None else _wrap(t.contiguous(), lay)
+               for t in (du_buf, dcoeff_buf, dwcon_buf, da_buf, db_buf, dc_buf)]
+        dx = lay.like(fill=0.0)
+        B.stencil_hdiff_vadv_jvp(u, coeff, wcon, a, b, c, dt, dx,
+                                 x=x if any(t is not None for t in tan[3:]) else None,
+                                 du=tan[0], dcoeff=tan[1], dwcon=tan[2], da=tan[3], db=tan[4], dc=tan[5])
+        return dx.buf
+
+    @staticmethod
     def backward(ctx, gx_buf):
+        if gx_buf is None:
+            return None, None, None, None, None, None, None
         lay, dt = ctx.meta
         x_lay = lay
         u, coeff, wcon, a, b, c, x = (_wrap(t, lay) for t in ctx.saved_tensors)

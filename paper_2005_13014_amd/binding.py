@@ -75,6 +75,8 @@ _SIGNATURES = {
     "stencil_hdiff_vadv": [_P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _C, _V],
     "stencil_hdiff_vadv_adjoint": [_P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P, _P,
                                    _P, _P, _C, _V],
+    "stencil_hdiff_vadv_jvp": [_P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P, _P, _P, _P,
+                               _C, _V],
     "stencil_program_run": [ctypes.POINTER(Program), _V],
     "stencil_last_error": [],
     "stencil_abi_version": [],
@@ -238,6 +240,16 @@ def stencil_hdiff_vadv_adjoint(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon
         _desc(u), _desc(coeff), _desc(wcon), _desc(a), _desc(b), _desc(c), float(dt), _desc(w),
         _desc(gu), _desc(gcoeff), _desc(gwcon), _desc(x), _desc(ga), _desc(gb), _desc(gc), _cfg(cfg),
         _stream(stream)))
+
+
+def stencil_hdiff_vadv_jvp(u, coeff, wcon, a, b, c, dt, dx, x=None, du=None, dcoeff=None, dwcon=None,
+                           da=None, db=None, dc=None, cfg=None, stream=None):
+    """Forward mode of x = vadv(hdiff(u)): the tangent dx in the direction
+    (du, dcoeff, dwcon, da, db, dc), None tangents being zero; x (the forward
+    result) is needed when any of da, db, dc is given."""
+    _check(lib().stencil_hdiff_vadv_jvp(
+        _desc(u), _desc(coeff), _desc(wcon), _desc(a), _desc(b), _desc(c), float(dt), _desc(x), _desc(du),
+        _desc(dcoeff), _desc(dwcon), _desc(da), _desc(db), _desc(dc), _desc(dx), _cfg(cfg), _stream(stream)))
 
 
 def stencil_program_run(prog, stream=None):

@@ -503,6 +503,55 @@ STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stenc
     return launch_status(launch_adjoint(u->dtype, x, scratch, st), "adjoint kernels");
 }
 
+STENCIL_API int stencil_hdiff_vadv_jvp(const stencil_field_t *u, const stencil_field_t *coeff,
+                                       const stencil_field_t *wcon, const stencil_field_t *a,
+                                       const stencil_field_t *b, const stencil_field_t *c, double dt,
+                                       const stencil_field_t *xf, const stencil_field_t *du,
+                                       const stencil_field_t *dcoeff, const stencil_field_t *dwcon,
+                                       const stencil_field_t *da, const stencil_field_t *db,
+                                       const stencil_field_t *dc, const stencil_field_t *dx,
+                                       const stencil_config_t *cfg, void *stream) {
+    // Inputs first, the output last (the alias check takes the last nout as outputs).
+    const stencil_field_t *fs[14];
+    const char *names[14];
+    int n = 0;
+    auto add = [&](const stencil_field_t *f, const char *name) { fs[n] = f; names[n++] = name; };
+    add(u, "u"); add(coeff, "coeff"); add(wcon, "wcon"); add(a, "a"); add(b, "b"); add(c, "c");
+    const bool matrix = da || db || dc;
+    if (matrix && !xf) return fail(STENCIL_E_NULL, "x (the forward result) is required for da, db, dc");
+    if (matrix) add(xf, "x");
+    if (du) add(du, "du");
+    if (dcoeff) add(dcoeff, "dcoeff");
+    if (dwcon) add(dwcon, "dwcon");
+    if (da) add(da, "da");
+    if (db) add(db, "db");
+    if (dc) add(dc, "dc");
+    add(dx, "dx");
+    TRY(check_call(fs, names, n, 1));
+    TRY(check_halo(u, "u", 2));
+    if (du) TRY(check_halo(du, "du", 2));
+    TRY(check_dt(dt));
+    (void)cfg;
+    if (empty(u)) return STENCIL_OK;
+    if (u->nk > KMAX_JVP) return fail(STENCIL_E_UNSUPPORTED, "jvp supports nk <= %d", KMAX_JVP);
+    if (!column_fits(u)) return fail(STENCIL_E_UNSUPPORTED, "jvp supports fields below 2 GiB");
+    JvpArgs v{};
+    v.u = u->origin; v.coeff = coeff->origin; v.wcon = wcon->origin;
+    v.a = a->origin; v.b = b->origin; v.c = c->origin;
+    v.x = matrix ? xf->origin : nullptr;
+    v.du = du ? du->origin : nullptr;
+    v.dcoeff = dcoeff ? dcoeff->origin : nullptr;
+    v.dwcon = dwcon ? dwcon->origin : nullptr;
+    v.da = da ? da->origin : nullptr;
+    v.db = db ? db->origin : nullptr;
+    v.dc = dc ? dc->origin : nullptr;
+    v.dx = dx->origin;
+    v.I = u->ni; v.J = u->nj; v.K = u->nk;
+    v.sj = static_cast<int>(u->sj); v.sk = static_cast<int>(u->sk);
+    v.dt = dt;
+    return launch_status(launch_jvp(u->dtype, v, static_cast<hipStream_t>(stream)), "jvp kernel");
+}
+
 STENCIL_API int stencil_probe_copy(const void *src, void *dst, int64_t nbytes, void *stream) {
     if (!src || !dst) return fail(STENCIL_E_NULL, "probe_copy: NULL pointer");
     if (nbytes < 0 || nbytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 ||

@@ -62,6 +62,20 @@ struct AdjointArgs {
 };
 constexpr int KMAX_ADJOINT = 96;
 size_t adjoint_scratch_bytes(int dtype, int sk, int K);
+
+// Forward mode (tangent) of the fused program.  u and du at interior
+// origins with a halo of at least 2; every other field at its interior
+// origin; all share (sj, sk).  Tangent pointers may be NULL (zero); x (the
+// forward solution) is read only when da, db or dc is given.  nk <= KMAX_JVP.
+struct JvpArgs {
+    const void *u, *coeff, *wcon, *a, *b, *c, *x;
+    const void *du, *dcoeff, *dwcon, *da, *db, *dc;
+    void *dx;
+    int I, J, K, sj, sk;
+    double dt;
+};
+constexpr int KMAX_JVP = 96;
+hipError_t launch_jvp(int dtype, const JvpArgs &a, hipStream_t st);
 hipError_t launch_adjoint(int dtype, const AdjointArgs &a, void *scratch, hipStream_t st);
 
 // Streaming copy used as the bandwidth probe (probe.hip).

@@ -113,6 +113,36 @@ def test_adjoint_matrix_gradient_checks():
     assert adjoint(empty[:10], x=empty[10], ga=empty[11], gb=empty[12], gc=empty[13]) == 0
 
 
+def jvp(fs, x=None, du=None, dcoeff=None, dwcon=None, da=None, db=None, dc=None, dt=10.0):
+    """fs: u, coeff, wcon, a, b, c, dx."""
+    r = ctypes.byref
+    opt = lambda f: r(f) if f is not None else None  # noqa: E731
+    return B.lib().stencil_hdiff_vadv_jvp(*[r(f) for f in fs[:6]], dt, opt(x), opt(du), opt(dcoeff),
+                                          opt(dwcon), opt(da), opt(db), opt(dc), r(fs[6]), None, None)
+
+
+def test_jvp_argument_checks():
+    fs = spaced(14)
+    base, (x, du, dcoeff, dwcon, da, db, dc) = fs[:7], fs[7:]
+    # the matrix tangents need the forward result
+    assert jvp(base, db=db) == 1
+    assert "forward result" in B.stencil_last_error()
+    # du needs the 2-cell halo that u has
+    assert jvp(base, du=fd(origin=du.origin, hi=1, hj=1, sj=du.sj, sk=du.sk)) == 5
+    # the output may not overlap a tangent
+    assert jvp(base[:6] + [fd(origin=dcoeff.origin + 64)], dcoeff=dcoeff) == 6
+    # shape mismatch of a tangent
+    assert jvp(base, dwcon=fd(origin=dwcon.origin, ni=15)) == 3
+    # more levels than the kernel's buckets hold
+    deep = spaced(7, nk=97)
+    assert jvp(deep) == 7
+    # an empty interior is a no-op that still validates every field
+    empty = spaced(14, nk=0)
+    assert jvp(empty[:7], x=empty[7], du=empty[8], dcoeff=empty[9], dwcon=empty[10], da=empty[11],
+               db=empty[12], dc=empty[13]) == 0
+    assert jvp(base, dt=float("nan")) == 9
+
+
 def test_null_descriptor_and_origin():
     u, c, o = spaced(3)
     assert hdiff(None, c, o) == 1

@@ -1,0 +1,153 @@
+"""Forward mode on the GPU: the hand-written tangent kernel against the FP64
+oracle's tangent (under the kernel's own limiter decisions for FP32 and
+bfloat16 storage), duality with the GPU reverse mode, subsets of tangent
+inputs, and torch forward-mode AD through the autograd wrapper (GPU only)."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import DT, SEED, TOL, halo_untouched, interior, limiter_masks, normwise, rms_rel
+from paper_2005_13014_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2005_13014_amd import binding as B  # noqa: E402
+from paper_2005_13014_amd import autograd as AG  # noqa: E402
+
+NAMES = ("u", "coeff", "wcon", "a", "b", "c")
+TKW = {"u": "du", "coeff": "dcoeff", "wcon": "dwcon", "a": "da", "b": "db", "c": "dc"}
+OKW = {"u": "du", "coeff": "dcoeff", "wcon": "dw", "a": "da", "b": "db", "c": "dc"}
+
+
+def note(*a):
+    print(*a, flush=True)
+
+
+def setup(ni, nj, nk, dtype, seed, tangents=NAMES):
+    f = inputs.fields(ni, nj, nk, 2, seed=seed, storage=dtype, loss=True)
+    rng = np.random.default_rng(seed + 7)
+    v = {n: inputs.round_to(rng.standard_normal(f[n].shape), dtype) for n in tangents}
+    g = {n: B.Field.from_numpy(f[n], 2, dtype) for n in NAMES + ("w",)}
+    gv = {n: B.Field.from_numpy(v[n], 2, dtype) for n in tangents}
+    return f, v, g, gv
+
+
+def gpu_forward(g):
+    x = g["u"].like(fill=0.0)
+    B.stencil_hdiff_vadv(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT, x)
+    return x
+
+
+def gpu_jvp(g, gv, x=None, canary=-7.0):
+    dx = g["u"].like(fill=canary)
+    if x is None and any(n in gv for n in ("a", "b", "c")):
+        x = gpu_forward(g)
+    B.stencil_hdiff_vadv_jvp(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT, dx, x=x,
+                             **{TKW[n]: gv[n] for n in gv})
+    torch.cuda.synchronize()
+    return dx
+
+
+def oracle_jvp(f, v, masks=None):
+    kx, ky = masks if masks is not None else (None, None)
+    return oracle.hdiff_vadv_jvp(f["u"], 2, f["coeff"], 2, f["wcon"], 2, f["a"], 2, f["b"], 2, f["c"], 2,
+                                 DT, hdu=2, hdcf=2, hdw=2, hdm=2, force_kx=kx, force_ky=ky,
+                                 **{OKW[n]: v[n] for n in v})
+
+
+def check(dx, ref, tol, label):
+    got = dx.to_numpy(interior=True)
+    err = normwise(got, ref)
+    note(label, "normwise %.2e rms %.2e" % (err, rms_rel(got, ref)))
+    assert err <= tol, err
+    assert halo_untouched(dx)
+
+
+# nk spans the four level buckets (<= 32, <= 64, <= 80, <= 96); the extents
+# give several tiles and ragged edges in i and j.
+@pytest.mark.parametrize("shape", [(64, 64, 60), (70, 13, 5), (3, 2, 1), (131, 9, 96), (65, 3, 80),
+                                   (17, 31, 2)])
+def test_jvp_fp64_matches_oracle(shape):
+    ni, nj, nk = shape
+    note("jvp f64", shape)
+    f, v, g, gv = setup(ni, nj, nk, "f64", SEED + 60)
+    check(gpu_jvp(g, gv), oracle_jvp(f, v), TOL["f64"], "jvp f64 %s" % (shape,))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("shape", [(64, 64, 60), (99, 17, 33), (130, 5, 80)])
+def test_jvp_low_precision_under_its_own_masks(dtype, shape):
+    # As for the adjoint: the tangent jumps where a limiter decision flips, so
+    # the reference takes the decisions of the kernel's arithmetic.
+    ni, nj, nk = shape
+    note("jvp", dtype, shape)
+    f, v, g, gv = setup(ni, nj, nk, dtype, SEED + 61)
+    ref = oracle_jvp(f, v, limiter_masks(f["u"], 2, dtype))
+    check(gpu_jvp(g, gv), ref, TOL[dtype], "jvp %s %s" % (dtype, shape))
+
+
+@pytest.mark.parametrize("subset", [("u",), ("coeff",), ("wcon",), ("a",), ("b",), ("c",),
+                                    ("coeff", "wcon", "b"), ("u", "c"), ()])
+def test_jvp_tangent_subsets(subset):
+    ni, nj, nk = 40, 11, 20
+    note("jvp subset", subset)
+    f, v, g, gv = setup(ni, nj, nk, "f64", SEED + 62, tangents=subset)
+    ref = oracle_jvp(f, v)
+    dx = gpu_jvp(g, gv)
+    if not subset:
+        assert np.all(dx.to_numpy(interior=True) == 0) and halo_untouched(dx)
+    else:
+        check(dx, ref, TOL["f64"], "jvp subset %s" % (subset,))
+
+
+def test_jvp_headline_size_f32():
+    # The size the benchmark times the reverse mode at, FP32 storage.
+    ni, nj, nk = 256, 256, 80
+    note("jvp f32 256x256x80")
+    f, v, g, gv = setup(ni, nj, nk, "f32", SEED + 63)
+    ref = oracle_jvp(f, v, limiter_masks(f["u"], 2, "f32"))
+    check(gpu_jvp(g, gv), ref, TOL["f32"], "jvp f32 256x256x80")
+
+
+def test_jvp_duality_with_gpu_adjoint():
+    # <w, J v> = <J^T w, v> with both sides from the GPU kernels.
+    ni, nj, nk = 70, 19, 37
+    f, v, g, gv = setup(ni, nj, nk, "f64", SEED + 64)
+    x = gpu_forward(g)
+    dx = gpu_jvp(g, gv, x=x)
+    grads = {n: g["u"].like(fill=0.0) for n in ("gu", "gcoeff", "gwcon", "ga", "gb", "gc")}
+    B.stencil_hdiff_vadv_adjoint(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT, g["w"],
+                                 grads["gu"], grads["gcoeff"], grads["gwcon"], x=x, ga=grads["ga"],
+                                 gb=grads["gb"], gc=grads["gc"])
+    torch.cuda.synchronize()
+    lhs = float((interior(f["w"], 2) * dx.to_numpy(interior=True)).sum())
+    terms = [float((grads["gu"].to_numpy() * v["u"]).sum())]
+    for n, gn in (("coeff", "gcoeff"), ("wcon", "gwcon"), ("a", "ga"), ("b", "gb"), ("c", "gc")):
+        terms.append(float((grads[gn].to_numpy(interior=True) * interior(v[n], 2)).sum()))
+    note("duality", lhs, sum(terms))
+    assert abs(lhs - sum(terms)) <= 1e-11 * sum(abs(t) for t in terms)
+
+
+def test_jvp_needs_forward_result_for_matrix_tangents():
+    f, v, g, gv = setup(9, 5, 6, "f64", SEED + 65, tangents=("b",))
+    dx = g["u"].like(fill=0.0)
+    with pytest.raises(RuntimeError):
+        B.stencil_hdiff_vadv_jvp(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT, dx, db=gv["b"])
+
+
+def test_forward_mode_autograd():
+    import torch.autograd.forward_ad as fwAD
+    ni, nj, nk = 70, 12, 40
+    f, v, g, gv = setup(ni, nj, nk, "f64", SEED + 66, tangents=("u", "a"))
+    lay = g["u"]
+    with fwAD.dual_level():
+        ub = fwAD.make_dual(g["u"].buf, gv["u"].buf)
+        ab = fwAD.make_dual(g["a"].buf, gv["a"].buf)
+        xb = AG.HdiffVadv.apply(ub, g["coeff"].buf, g["wcon"].buf, ab, g["b"].buf, g["c"].buf, (lay, DT))
+        tangent = fwAD.unpack_dual(xb).tangent
+    ref = gpu_jvp(g, gv, canary=0.0)
+    assert torch.equal(tangent, ref.buf)
