@@ -167,7 +167,8 @@ int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field_t *coeff,
  * overwritten; the four 3-cell corner notches of the ring receive 0),
  * gcoeff and gwcon (interior); optionally ga, gb, gc (interior; NULL skips
  * each, and x may be NULL when all three are NULL).  Uses library-owned
- * device scratch. */
+ * device scratch.  nk <= 96 and fields below 2 GiB in the compute type
+ * (FP32 for bfloat16 storage); STENCIL_E_UNSUPPORTED otherwise. */
 int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stencil_field_t *coeff,
                                const stencil_field_t *wcon, const stencil_field_t *a,
                                const stencil_field_t *b, const stencil_field_t *c, double dt,

@@ -11,7 +11,7 @@
 //        gh(k)  = lam(k) + Fhat(k-1/2) wbar(k-1/2)/2 + Fhat(k+1/2) wbar(k+1/2)/2
 //        gwcon(k) =        Fhat(k-1/2) hbar(k-1/2)/2 + Fhat(k+1/2) hbar(k+1/2)/2
 //      (wbar, hbar: face means of wcon and h); gh goes to scratch;
-//   3. k_hdiff_adjoint, one workgroup per (tile, level): with g = -coeff gh,
+//   3. k_hdiff_adjoint, one workgroup per (tile, run of levels): with g = -coeff gh,
 //      the transposed update, limited flux and Laplacian stencils, staged
 //      through LDS, give gu on the interior and its 2-cell ring and
 //      gcoeff = -gh (flx - flx(i-1) + fly - fly(j-1)) on the interior.
@@ -250,8 +250,9 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
 
 // ---------------------------------------------------------------------------
 // hdiff adjoint.  Tile of 64 x TJ output points of the extended domain
-// [-2, I+2) x [-2, J+2) at one level, local coordinates (lx, ly) = (i - x0,
-// j - y0).  Stages (each ends with a barrier):
+// [-2, I+2) x [-2, J+2), local coordinates (lx, ly) = (i - x0, j - y0); a
+// workgroup marches over KC consecutive levels of its tile.  Per level
+// (each stage ends with a barrier):
 //   U  u on lx in [-3, 67), ly in [-3, TJ+3) (0 outside u's 2-cell halo)
 //   G  g = -coeff gh on lx in [-2, 66), ly in [-2, TJ+2) (0 outside the interior)
 //   L  lap on lx in [-2, 66), ly in [-2, TJ+2)
@@ -260,93 +261,156 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
 //   H  glap = gfx(i-1) - gfx(i) + gfy(j-1) - gfy(j) on lx in [-1, 65), ly in [-1, TJ+1)
 // then gu = gh (interior) - glap(j-1) - glap(i-1) + 4 glap - glap(i+1) - glap(j+1)
 // and gcoeff = -gh (flx - flx(i-1) + fly - fly(j-1)).
+// The global values of U and G (and gh at the outputs) for the next PF
+// levels are requested into a register ring before a level's stages run, so
+// their latency overlaps that level's LDS work.  Loads address clamped,
+// valid cells; a select applies the zero outside the domain.
 // ---------------------------------------------------------------------------
-template <class T, int TJ>
+template <class T, int TJ, int PF, int KC>
 __global__ __launch_bounds__(256) void k_hdiff_adjoint(AdjArgs p, int nbi, int ntiles) {
+#pragma clang fp contract(off)
     using S = Storage<T>;
     using C = typename S::C;
+    using IO = BufIO<T>;
+    using IOC = BufIO<C>;
+    using R = typename IO::R;
+    using RC = typename IOC::R;
     constexpr int TI = 64;
     constexpr int UX = TI + 6, UY = TJ + 6;     // offset 3
     constexpr int GX = TI + 4, GY = TJ + 4;     // offset 2 (g and lap)
     constexpr int XX = TI + 3, XY = TJ + 2;     // x-faces: lx + 2, ly + 1
     constexpr int YX = TI + 2, YY = TJ + 3;     // y-faces: lx + 1, ly + 2
     constexpr int HX = TI + 2, HY = TJ + 2;     // glap: lx + 1, ly + 1
+    constexpr int NU = (UY * UX + 255) / 256, NG = (GY * GX + 255) / 256, NO = (TJ + 3) / 4;
+    constexpr uint32_t ES = sizeof(T), ESC = sizeof(C);
     __shared__ C su[UY * UX], sg[GY * GX], sl[GY * GX];
     __shared__ C sgx[XY * XX], sfx[XY * XX], sgy[YY * YX], sfy[YY * YX], sh[HY * HX];
 
-    const T *__restrict__ u = static_cast<const T *>(p.u);
-    const T *__restrict__ coeff = static_cast<const T *>(p.coeff);
-    const C *__restrict__ gh = static_cast<const C *>(p.gh);
     T *__restrict__ gu = static_cast<T *>(p.gu);
     T *__restrict__ gcoeff = static_cast<T *>(p.gcoeff);
-    const int I = p.I, J = p.J, sj = p.sj;
-    // Workgroups numbered level-major: consecutive positions are neighbouring
-    // tiles of one level, kept on one XCD so their shared halo rows meet in its L2.
+    const int I = p.I, J = p.J, K = p.K, sj = p.sj;
+    // Workgroups numbered chunk-major: consecutive positions are neighbouring
+    // tiles of one level range, kept on one XCD so their shared halo rows
+    // meet in its L2.
     const int pos = xcd_tile(blockIdx.x, gridDim.x);
-    const int tile = pos % ntiles, k = pos / ntiles;
+    const int tile = pos % ntiles, chunk = pos / ntiles;
+    const int k0 = chunk * KC, k1 = min(K, k0 + KC);
     const int bi = tile % nbi, bj = tile / nbi;
     const int x0 = -2 + bi * TI, y0 = -2 + bj * TJ;
-    const int ko = k * p.sk;
     const int tid = threadIdx.x;
 
-    for (int e = tid; e < UY * UX; e += 256) {
+    // u from its cell (-2, -2, 0); coeff and gh from the interior origin.
+    const long long cells = static_cast<long long>(K - 1) * p.sk;
+    const auto ru = make_rsrc(static_cast<const T *>(p.u) - 2 - 2 * sj,
+                              static_cast<uint32_t>(((I + 3) + (J + 3) * static_cast<long long>(sj) + cells + 1) * ES));
+    const uint32_t col = static_cast<uint32_t>((I - 1) + (J - 1) * static_cast<long long>(sj) + cells + 1);
+    const auto rcf = make_rsrc(p.coeff, col * ES);
+    const auto rgh = make_rsrc(p.gh, col * ESC);
+    uint32_t vu[NU], vg[NG], vo[NO];
+    bool okv[NU], okg[NG], inner[NO];
+#pragma unroll
+    for (int n = 0; n < NU; ++n) {
+        const int e = min(tid + 256 * n, UY * UX - 1);
         const int i = x0 - 3 + e % UX, j = y0 - 3 + e / UX;
-        su[e] = (i >= -2 && i < I + 2 && j >= -2 && j < J + 2) ? S::load(u + i + j * sj + ko) : C(0);
+        okv[n] = i >= -2 && i < I + 2 && j >= -2 && j < J + 2;
+        vu[n] = static_cast<uint32_t>(min(max(i, -2), I + 1) + 2 + (min(max(j, -2), J + 1) + 2) * sj);
     }
-    for (int e = tid; e < GY * GX; e += 256) {
+#pragma unroll
+    for (int n = 0; n < NG; ++n) {
+        const int e = min(tid + 256 * n, GY * GX - 1);
         const int i = x0 - 2 + e % GX, j = y0 - 2 + e / GX;
-        C g = C(0);
-        if (i >= 0 && i < I && j >= 0 && j < J) {
-            const int o = i + j * sj + ko;
-            g = -S::load(coeff + o) * gh[o];
+        okg[n] = i >= 0 && i < I && j >= 0 && j < J;
+        vg[n] = static_cast<uint32_t>(min(max(i, 0), I - 1) + min(max(j, 0), J - 1) * sj);
+    }
+#pragma unroll
+    for (int n = 0; n < NO; ++n) {
+        const int i = x0 + (tid & 63), j = y0 + (tid >> 6) + 4 * n;
+        inner[n] = i >= 0 && i < I && j >= 0 && j < J;
+        vo[n] = static_cast<uint32_t>(min(max(i, 0), I - 1) + min(max(j, 0), J - 1) * sj);
+    }
+
+    R rum[PF][NU], rcv[PF][NG];
+    RC rgv[PF][NG], rov[PF][NO];
+    auto load = [&](int q, int k) {
+        const uint32_t ko = static_cast<uint32_t>(k) * static_cast<uint32_t>(p.sk);
+#pragma unroll
+        for (int n = 0; n < NU; ++n) rum[q][n] = IO::load_raw(ru, (vu[n] + ko) * ES, 0);
+#pragma unroll
+        for (int n = 0; n < NG; ++n) {
+            rcv[q][n] = IO::load_raw(rcf, (vg[n] + ko) * ES, 0);
+            rgv[q][n] = IOC::load_raw(rgh, (vg[n] + ko) * ESC, 0);
         }
-        sg[e] = g;
-    }
-    __syncthreads();
-    for (int e = tid; e < GY * GX; e += 256) {
-        const C *c = &su[(e / GX + 1) * UX + e % GX + 1];
-        sl[e] = C(4) * c[0] - c[1] - c[-1] - c[UX] - c[-UX];
-    }
-    __syncthreads();
-    for (int e = tid; e < XY * XX; e += 256) {
-        const int lx = e % XX - 2, ly = e / XX - 1;
-        const int gl = (ly + 2) * GX + lx + 2, ul = (ly + 3) * UX + lx + 3;
-        const C f = sl[gl + 1] - sl[gl];
-        const C du = su[ul + 1] - su[ul];
-        const bool kept = !(f * du > C(0));
-        sfx[e] = kept ? f : C(0);
-        sgx[e] = kept ? sg[gl] - sg[gl + 1] : C(0);
-    }
-    for (int e = tid; e < YY * YX; e += 256) {
-        const int lx = e % YX - 1, ly = e / YX - 2;
-        const int gl = (ly + 2) * GX + lx + 2, ul = (ly + 3) * UX + lx + 3;
-        const C f = sl[gl + GX] - sl[gl];
-        const C du = su[ul + UX] - su[ul];
-        const bool kept = !(f * du > C(0));
-        sfy[e] = kept ? f : C(0);
-        sgy[e] = kept ? sg[gl] - sg[gl + GX] : C(0);
-    }
-    __syncthreads();
-    for (int e = tid; e < HY * HX; e += 256) {
-        const int lx = e % HX - 1, ly = e / HX - 1;
-        const int xi = (ly + 1) * XX + lx + 2, yi = (ly + 2) * YX + lx + 1;
-        sh[e] = sgx[xi - 1] - sgx[xi] + sgy[yi - YX] - sgy[yi];
-    }
-    __syncthreads();
-    for (int ly = tid >> 6; ly < TJ; ly += 4) {
-        const int lx = tid & 63;
-        const int i = x0 + lx, j = y0 + ly;
-        if (i < I + 2 && j < J + 2) {
-            const int hc = (ly + 1) * HX + lx + 1;
-            const bool inner = i >= 0 && i < I && j >= 0 && j < J;
-            const int o = i + j * sj + ko;
-            const C ghv = inner ? gh[o] : C(0);
-            const C g = ghv - sh[hc - HX] - sh[hc - 1] + C(4) * sh[hc] - sh[hc + 1] - sh[hc + HX];
-            S::store(gu + o, g);
-            if (inner) {
+#pragma unroll
+        for (int n = 0; n < NO; ++n) rov[q][n] = IOC::load_raw(rgh, (vo[n] + ko) * ESC, 0);
+    };
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+        if (k0 + q < k1) load(q, k0 + q);
+
+    for (int kk = k0; kk < k1; kk += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = kk + q;
+            if (k >= k1) break;
+#pragma unroll
+            for (int n = 0; n < NU; ++n)
+                if (tid + 256 * n < UY * UX) su[tid + 256 * n] = okv[n] ? IO::cvt(rum[q][n]) : C(0);
+#pragma unroll
+            for (int n = 0; n < NG; ++n)
+                if (tid + 256 * n < GY * GX)
+                    sg[tid + 256 * n] = okg[n] ? -IO::cvt(rcv[q][n]) * IOC::cvt(rgv[q][n]) : C(0);
+            C gho[NO];
+#pragma unroll
+            for (int n = 0; n < NO; ++n) gho[n] = inner[n] ? IOC::cvt(rov[q][n]) : C(0);
+            if (k + PF < k1) load(q, k + PF);
+            __syncthreads();
+            for (int e = tid; e < GY * GX; e += 256) {
+                const C *c = &su[(e / GX + 1) * UX + e % GX + 1];
+                sl[e] = C(4) * c[0] - c[1] - c[-1] - c[UX] - c[-UX];
+            }
+            __syncthreads();
+            for (int e = tid; e < XY * XX; e += 256) {
+                const int lx = e % XX - 2, ly = e / XX - 1;
+                const int gl = (ly + 2) * GX + lx + 2, ul = (ly + 3) * UX + lx + 3;
+                const C f = sl[gl + 1] - sl[gl];
+                const C du = su[ul + 1] - su[ul];
+                const bool kept = !(f * du > C(0));
+                sfx[e] = kept ? f : C(0);
+                sgx[e] = kept ? sg[gl] - sg[gl + 1] : C(0);
+            }
+            for (int e = tid; e < YY * YX; e += 256) {
+                const int lx = e % YX - 1, ly = e / YX - 2;
+                const int gl = (ly + 2) * GX + lx + 2, ul = (ly + 3) * UX + lx + 3;
+                const C f = sl[gl + GX] - sl[gl];
+                const C du = su[ul + UX] - su[ul];
+                const bool kept = !(f * du > C(0));
+                sfy[e] = kept ? f : C(0);
+                sgy[e] = kept ? sg[gl] - sg[gl + GX] : C(0);
+            }
+            __syncthreads();
+            for (int e = tid; e < HY * HX; e += 256) {
+                const int lx = e % HX - 1, ly = e / HX - 1;
                 const int xi = (ly + 1) * XX + lx + 2, yi = (ly + 2) * YX + lx + 1;
-                const C div = sfx[xi] - sfx[xi - 1] + sfy[yi] - sfy[yi - YX];
-                S::store(gcoeff + o, -ghv * div);
+                sh[e] = sgx[xi - 1] - sgx[xi] + sgy[yi - YX] - sgy[yi];
+            }
+            __syncthreads();
+            const long long ko = static_cast<long long>(k) * p.sk;
+#pragma unroll
+            for (int n = 0; n < NO; ++n) {
+                const int lx = tid & 63, ly = (tid >> 6) + 4 * n;
+                const int i = x0 + lx, j = y0 + ly;
+                if (ly < TJ && i < I + 2 && j < J + 2) {
+                    const int hc = (ly + 1) * HX + lx + 1;
+                    const long long o = i + static_cast<long long>(j) * sj + ko;
+                    const C ghv = gho[n];
+                    const C g = ghv - sh[hc - HX] - sh[hc - 1] + C(4) * sh[hc] - sh[hc + 1] - sh[hc + HX];
+                    S::store(gu + o, g);
+                    if (inner[n]) {
+                        const int xi = (ly + 1) * XX + lx + 2, yi = (ly + 2) * YX + lx + 1;
+                        const C div = sfx[xi] - sfx[xi - 1] + sfy[yi] - sfy[yi - YX];
+                        S::store(gcoeff + o, -ghv * div);
+                    }
+                }
             }
         }
     }
@@ -394,13 +458,14 @@ static hipError_t adjoint_run(AdjArgs a, void *scratch, hipStream_t st) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     // Rows per hdiff-adjoint tile: 8 (two per thread) where the staged tile
-    // fits often enough in LDS; FP64's twice larger tile keeps 4.
-    constexpr int HTJ = std::is_same<T, double>::value ? 4 : 8;
+    // fits often enough in LDS; FP64's twice larger tile keeps 4.  Each
+    // workgroup marches over HKC levels with HPF levels in flight.
+    constexpr int HTJ = std::is_same<T, double>::value ? 4 : 8, HPF = 2, HKC = 8;
     const int nbi = (a.I + 4 + 63) / 64, nbj = (a.J + 4 + HTJ - 1) / HTJ;
-    const long long blocks = static_cast<long long>(nbi) * nbj * a.K;
+    const long long blocks = static_cast<long long>(nbi) * nbj * ((a.K + HKC - 1) / HKC);
     if (blocks > 2147483647LL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_hdiff_adjoint<T, HTJ>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a,
-                       nbi, nbi * nbj);
+    hipLaunchKernelGGL((k_hdiff_adjoint<T, HTJ, HPF, HKC>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                       st, a, nbi, nbi * nbj);
     return hipGetLastError();
 }
 

@@ -486,6 +486,13 @@ STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stenc
     if (u->nk > KMAX_ADJOINT)
         return fail(STENCIL_E_UNSUPPORTED, "adjoint supports nk <= %d", KMAX_ADJOINT);
     if (u->nk > 65535) return fail(STENCIL_E_UNSUPPORTED, "nk too large");
+    {
+        // 32-bit buffer offsets, also into the compute-type scratch (FP32 for bfloat16 storage)
+        const long long cells = static_cast<long long>(u->ni + 3) + static_cast<long long>(u->nj + 3) * u->sj +
+                                static_cast<long long>(u->nk - 1) * u->sk + 1;
+        if (cells * (u->dtype == STENCIL_F64 ? 8 : 4) >= 2147483647LL)
+            return fail(STENCIL_E_UNSUPPORTED, "adjoint supports fields below 2 GiB (in the compute type)");
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     AdjointArgs x{};
     x.u = u->origin; x.coeff = coeff->origin; x.wcon = wcon->origin;
