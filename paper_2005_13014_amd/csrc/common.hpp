@@ -120,6 +120,7 @@ struct HdiffArgs {
     void *out;
     int I, J, K, sj, sk;
     int nbi, nbj;           // tiles in i and j
+    int kc;                 // levels per workgroup (the k range is split into runs of kc)
     uint32_t u_bytes;       // addressable bytes from u's cell (-2, -2, 0)
     uint32_t col_bytes;     // addressable bytes from an interior origin
 };

@@ -8,7 +8,11 @@
 // subexpression elimination does in the paper: the Laplacian at the lane's
 // own column is computed once for the UJ + 2 rows it touches, and each
 // j-flux is computed once and used by the two points on either side of it.
-// The inputs of the next PF levels are prefetched into registers.
+// The inputs of the next PF levels are prefetched into registers (raw stored
+// bits, widened where used).  The k range is split into runs of kc levels,
+// one per workgroup, so that small grids still give the chip enough
+// workgroups.
+#include <algorithm>
 #include <type_traits>
 
 #include "column.hpp"
@@ -42,7 +46,8 @@ __global__ __launch_bounds__(64 * TJ) void k_hdiff(HdiffArgs p) {
 
     const int tid = threadIdx.x, ti = tid & 63;
     const int tj = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int pos = xcd_tile(blockIdx.x, gridDim.x), ntiles = p.nbi * p.nbj;
+    const int t = pos % ntiles, run = pos / ntiles;
     const int bi = t % p.nbi, bj = t / p.nbi;
     const int i0 = bi * TI, j0 = bj * RJ;
     const int gi = i0 + ti;
@@ -86,35 +91,36 @@ __global__ __launch_bounds__(64 * TJ) void k_hdiff(HdiffArgs p) {
         vcol[v] = static_cast<uint32_t>(min(gi, I - 1) + min(gj, J - 1) * sj) * ES;
     }
 
-    C rum[PF][MR], rus[PF], rcf_[PF][UJ];
+    using R = typename IO::R;
+    R rum[PF][MR], rus[PF], rcf_[PF][UJ];
     auto load = [&](int q, int k) {
         const uint32_t so = static_cast<uint32_t>(k) * skb;
 #pragma unroll
         for (int m = 0; m < MR; ++m)
-            if (mrow[m]) rum[q][m] = IO::load(ru, vmain[m], so);
-        if (side_wave) rus[q] = IO::load(ru, vside, so);
+            if (mrow[m]) rum[q][m] = IO::load_raw(ru, vmain[m], so);
+        if (side_wave) rus[q] = IO::load_raw(ru, vside, so);
 #pragma unroll
-        for (int v = 0; v < UJ; ++v) rcf_[q][v] = IO::load(rcf, vcol[v], so);
+        for (int v = 0; v < UJ; ++v) rcf_[q][v] = IO::load_raw(rcf, vcol[v], so);
     };
 
-    const int K = p.K;
+    const int kb = run * p.kc, K = min(p.K, kb + p.kc);
 #pragma unroll
     for (int q = 0; q < PF; ++q)
-        if (q < K) load(q, q);
+        if (kb + q < K) load(q, kb + q);
 
-    for (int k0 = 0; k0 < K; k0 += PF) {
+    for (int k0 = kb; k0 < K; k0 += PF) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int k = k0 + q;
             if (k < K) {
-                C *tb = tile[q & 1];  // PF is even, so q & 1 == k & 1
+                C *tb = tile[q & 1];  // PF is even, so q & 1 == (k - kb) & 1
 #pragma unroll
                 for (int m = 0; m < MR; ++m)
-                    if (mrow[m]) tb[lmain[m]] = rum[q][m];
-                if (side_wave) tb[lside] = rus[q];
+                    if (mrow[m]) tb[lmain[m]] = IO::cvt(rum[q][m]);
+                if (side_wave) tb[lside] = IO::cvt(rus[q]);
                 C cf[UJ];
 #pragma unroll
-                for (int v = 0; v < UJ; ++v) cf[v] = rcf_[q][v];
+                for (int v = 0; v < UJ; ++v) cf[v] = IO::cvt(rcf_[q][v]);
                 if (k + PF < K) load(q, k + PF);
                 __syncthreads();
 
@@ -152,6 +158,7 @@ __global__ __launch_bounds__(64 * TJ) void k_hdiff(HdiffArgs p) {
 
 template <class T, int TJ, int UJ, int PF, class TO = T>
 static hipError_t launch_hdiff_t(HdiffArgs a, hipStream_t st) {
+    if (a.I <= 0 || a.J <= 0 || a.K <= 0) return hipSuccess;
     a.nbi = (a.I + 63) / 64;
     a.nbj = (a.J + TJ * UJ - 1) / (TJ * UJ);
     const long long es = sizeof(T);
@@ -159,7 +166,15 @@ static hipError_t launch_hdiff_t(HdiffArgs a, hipStream_t st) {
                                        static_cast<long long>(a.K - 1) * a.sk + 1) * es);
     a.col_bytes = static_cast<uint32_t>(((a.I - 1) + static_cast<long long>(a.J - 1) * a.sj +
                                          static_cast<long long>(a.K - 1) * a.sk + 1) * es);
-    hipLaunchKernelGGL((k_hdiff<T, TO, TJ, UJ, PF>), dim3(a.nbi * a.nbj), dim3(64 * TJ), 0, st, a);
+    // Runs of levels: enough workgroups for eight per CU on 256 CUs, each run
+    // a multiple of PF and at least 2 PF levels long.
+    const long long tiles = static_cast<long long>(a.nbi) * a.nbj;
+    const long long runs = std::max(1LL, std::min<long long>((2048 + tiles - 1) / tiles, a.K / (2 * PF)));
+    a.kc = static_cast<int>((a.K + runs - 1) / runs + PF - 1) / PF * PF;
+    const long long blocks = tiles * ((a.K + a.kc - 1) / a.kc);
+    if (blocks > 2147483647LL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_hdiff<T, TO, TJ, UJ, PF>), dim3(static_cast<unsigned>(blocks)), dim3(64 * TJ), 0, st,
+                       a);
     return hipGetLastError();
 }
 
