@@ -121,6 +121,7 @@ uint64_t signature(const stencil_program_t *prog, hipStream_t st) {
     uint64_t h = 1469598103934665603ULL;
     h = fnv(h, &prog->nsub, sizeof(prog->nsub));
     h = fnv(h, &prog->stages, sizeof(prog->stages));
+    h = fnv(h, &prog->flags, sizeof(prog->flags));  // the flags choose the kernel variant
     h = fnv(h, &prog->dt, sizeof(double) * 4);
     h = fnv(h, &st, sizeof(st));
     for (int s = 0; s < prog->nsub; ++s) {
