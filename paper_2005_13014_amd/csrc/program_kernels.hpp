@@ -30,9 +30,10 @@ struct HgradBatch {
 // staged in LDS (each wave loads its own row, which holds its centre values;
 // waves 0 and 1 also load the rows above and below the tile, wave 2 the side
 // columns), the horizontal neighbours are read from the tile and the vertical
-// ones are kept in registers.  Loads run two levels ahead.
-template <class T>
+// ones are kept in registers.  Loads run PF levels ahead.
+template <class T, int PF = 8>
 __global__ __launch_bounds__(256) void k_hgrad_batch(HgradBatch b) {
+    static_assert(PF % 2 == 0, "the LDS tile alternates with the ring slot");
     using S = Storage<T>;
     using C = typename S::C;
     using IO = BufIO<T>;
@@ -70,46 +71,50 @@ __global__ __launch_bounds__(256) void k_hgrad_batch(HgradBatch b) {
     const uint32_t vz = static_cast<uint32_t>(min(gi, I - 1) + min(gj, J - 1) * sj) * ES;
     const uint32_t skb = static_cast<uint32_t>(sb.sk) * ES;
 
-    // Register ring rotated every level: (own0, two0) hold level k, (own1, two1) level k + 1.
-    // Raw stored bits, widened where used.
+    // Register ring of the next PF levels (raw stored bits, widened where
+    // used): slot q holds level k with k % PF == q.
     using R = typename IO::R;
-    R own0 = R(0), two0 = R(0), own1 = R(0), two1 = R(0);
-    auto load = [&](R &own, R &tw, int k) {
-        const uint32_t so = static_cast<uint32_t>(k) * skb;
-        own = IO::load_raw(ry, v_own, so);
-        if (two) tw = IO::load_raw(ry, v_two, so);
+    R own[PF], tw[PF];
+    // Levels past the top are clamped to it (their values are never used),
+    // so no load sits behind a branch whose join would wait for it.
+    auto load = [&](int q, int k) {
+        const uint32_t so = static_cast<uint32_t>(min(k, K - 1)) * skb;
+        own[q] = IO::load_raw(ry, v_own, so);
+        tw[q] = IO::load_raw(ry, v_two, so);
     };
-    load(own0, two0, 0);
-    if (K > 1) load(own1, two1, 1);
+#pragma unroll
+    for (int q = 0; q < PF; ++q) load(q, q);
 
     const C bh = static_cast<C>(b.beta_h), bv = static_cast<C>(b.beta_v), half = C(0.5);
-    C y_dn = C(0), y_c = IO::cvt(own0);
-    for (int k = 0; k < K; ++k) {
-        C *tb = &tile[(k & 1) * TILE];
-        tb[l_own] = IO::cvt(own0);
-        if (two) tb[l_two] = IO::cvt(two0);
-        const C y_up = k + 1 < K ? IO::cvt(own1) : C(0);
-        // rotate: level k + 1 moves down, level k + 2 is requested
-        own0 = own1;
-        two0 = two1;
-        if (k + 2 < K) load(own1, two1, k + 2);
-        __syncthreads();
-        const C *c = &tb[(w + 1) * PI + ti + 1];
-        const C gi_ = half * (c[1] - c[-1]);
-        const C gj_ = half * (c[PI] - c[-PI]);
-        C gk;
-        if (K == 1)
-            gk = C(0);
-        else if (k == 0)
-            gk = y_up - y_c;
-        else if (k == K - 1)
-            gk = y_c - y_dn;
-        else
-            gk = half * (y_up - y_dn);
-        const C z = y_c - bh * (gi_ + gj_) - bv * gk;
-        if (active) IO::template store_d<2>(rz, vz, static_cast<uint32_t>(k) * skb, static_cast<double>(z));
-        y_dn = y_c;
-        y_c = y_up;
+    C y_dn = C(0), y_c = IO::cvt(own[0]);
+    for (int k0 = 0; k0 < K; k0 += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = k0 + q;
+            if (k >= K) break;
+            C *tb = &tile[(q & 1) * TILE];  // PF is even: q & 1 == k & 1
+            tb[l_own] = IO::cvt(own[q]);
+            if (two) tb[l_two] = IO::cvt(tw[q]);
+            const C y_up = k + 1 < K ? IO::cvt(own[(q + 1) % PF]) : C(0);
+            load(q, k + PF);
+            __syncthreads();
+            const C *c = &tb[(w + 1) * PI + ti + 1];
+            const C gi_ = half * (c[1] - c[-1]);
+            const C gj_ = half * (c[PI] - c[-PI]);
+            C gk;
+            if (K == 1)
+                gk = C(0);
+            else if (k == 0)
+                gk = y_up - y_c;
+            else if (k == K - 1)
+                gk = y_c - y_dn;
+            else
+                gk = half * (y_up - y_dn);
+            const C z = y_c - bh * (gi_ + gj_) - bv * gk;
+            if (active) IO::template store_d<2>(rz, vz, static_cast<uint32_t>(k) * skb, static_cast<double>(z));
+            y_dn = y_c;
+            y_c = y_up;
+        }
     }
 }
 
