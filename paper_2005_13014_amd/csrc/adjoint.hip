@@ -15,6 +15,7 @@
 //      the transposed update, limited flux and Laplacian stencils, staged
 //      through LDS, give gu on the interior and its 2-cell ring and
 //      gcoeff = -gh (flx - flx(i-1) + fly - fly(j-1)) on the interior.
+#include <algorithm>
 #include <type_traits>
 
 #include "column.hpp"
@@ -251,7 +252,7 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
 // ---------------------------------------------------------------------------
 // hdiff adjoint.  Tile of 64 x TJ output points of the extended domain
 // [-2, I+2) x [-2, J+2), local coordinates (lx, ly) = (i - x0, j - y0); a
-// workgroup marches over KC consecutive levels of its tile.  Per level
+// workgroup marches over kc consecutive levels of its tile.  Per level
 // (each stage ends with a barrier):
 //   U  u on lx in [-3, 67), ly in [-3, TJ+3) (0 outside u's 2-cell halo)
 //   G  g = -coeff gh on lx in [-2, 66), ly in [-2, TJ+2) (0 outside the interior)
@@ -266,8 +267,8 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
 // their latency overlaps that level's LDS work.  Loads address clamped,
 // valid cells; a select applies the zero outside the domain.
 // ---------------------------------------------------------------------------
-template <class T, int TJ, int PF, int KC>
-__global__ __launch_bounds__(256) void k_hdiff_adjoint(AdjArgs p, int nbi, int ntiles) {
+template <class T, int TJ, int PF>
+__global__ __launch_bounds__(256) void k_hdiff_adjoint(AdjArgs p, int nbi, int ntiles, int kc) {
 #pragma clang fp contract(off)
     using S = Storage<T>;
     using C = typename S::C;
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(256) void k_hdiff_adjoint(AdjArgs p, int nbi, int n
     // meet in its L2.
     const int pos = xcd_tile(blockIdx.x, gridDim.x);
     const int tile = pos % ntiles, chunk = pos / ntiles;
-    const int k0 = chunk * KC, k1 = min(K, k0 + KC);
+    const int k0 = chunk * kc, k1 = min(K, k0 + kc);
     const int bi = tile % nbi, bj = tile / nbi;
     const int x0 = -2 + bi * TI, y0 = -2 + bj * TJ;
     const int tid = threadIdx.x;
@@ -459,13 +460,19 @@ static hipError_t adjoint_run(AdjArgs a, void *scratch, hipStream_t st) {
     if (e != hipSuccess) return e;
     // Rows per hdiff-adjoint tile: 8 (two per thread) where the staged tile
     // fits often enough in LDS; FP64's twice larger tile keeps 4.  Each
-    // workgroup marches over HKC levels with HPF levels in flight.
-    constexpr int HTJ = std::is_same<T, double>::value ? 4 : 8, HPF = 2, HKC = 8;
+    // workgroup marches over kc levels with HPF levels in flight; kc is chosen
+    // against the resident workgroup count (a mostly empty last round of
+    // workgroups costs nearly as much as a full one).
+    constexpr int HTJ = std::is_same<T, double>::value ? 4 : 8, HPF = 2;
     const int nbi = (a.I + 4 + 63) / 64, nbj = (a.J + 4 + HTJ - 1) / HTJ;
-    const long long blocks = static_cast<long long>(nbi) * nbj * ((a.K + HKC - 1) / HKC);
+    const long long tiles = static_cast<long long>(nbi) * nbj;
+    auto kern = k_hdiff_adjoint<T, HTJ, HPF>;
+    const long long slots = resident_workgroups(reinterpret_cast<const void *>(kern), 256);
+    const int kc = level_run(tiles, slots, a.K, 1, 1, HPF);
+    const long long blocks = tiles * ((a.K + kc - 1) / kc);
     if (blocks > 2147483647LL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_hdiff_adjoint<T, HTJ, HPF, HKC>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
-                       st, a, nbi, nbi * nbj);
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a, nbi,
+                       static_cast<int>(tiles), kc);
     return hipGetLastError();
 }
 

@@ -166,15 +166,15 @@ static hipError_t launch_hdiff_t(HdiffArgs a, hipStream_t st) {
                                        static_cast<long long>(a.K - 1) * a.sk + 1) * es);
     a.col_bytes = static_cast<uint32_t>(((a.I - 1) + static_cast<long long>(a.J - 1) * a.sj +
                                          static_cast<long long>(a.K - 1) * a.sk + 1) * es);
-    // Runs of levels: enough workgroups for eight per CU on 256 CUs, each run
-    // a multiple of PF and at least 2 PF levels long.
+    // Runs of levels sized against the resident workgroups, each a multiple
+    // of PF and at least 2 PF levels long.
     const long long tiles = static_cast<long long>(a.nbi) * a.nbj;
-    const long long runs = std::max(1LL, std::min<long long>((2048 + tiles - 1) / tiles, a.K / (2 * PF)));
-    a.kc = static_cast<int>((a.K + runs - 1) / runs + PF - 1) / PF * PF;
+    auto kern = k_hdiff<T, TO, TJ, UJ, PF>;
+    const long long slots = resident_workgroups(reinterpret_cast<const void *>(kern), 64 * TJ);
+    a.kc = level_run(tiles, slots, a.K, PF, 2 * PF, PF);
     const long long blocks = tiles * ((a.K + a.kc - 1) / a.kc);
     if (blocks > 2147483647LL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_hdiff<T, TO, TJ, UJ, PF>), dim3(static_cast<unsigned>(blocks)), dim3(64 * TJ), 0, st,
-                       a);
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(blocks)), dim3(64 * TJ), 0, st, a);
     return hipGetLastError();
 }
 

@@ -2,6 +2,8 @@
 // and storage type).  Launchers enqueue on `st` and return the launch status.
 #pragma once
 
+#include <algorithm>
+
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
@@ -62,6 +64,27 @@ struct AdjointArgs {
 };
 constexpr int KMAX_ADJOINT = 96;
 size_t adjoint_scratch_bytes(int dtype, int sk, int K);
+
+// Levels per workgroup for a kernel that splits each tile's k range into runs:
+// the multiple of `step` (at least min_len, at most K rounded up) that
+// minimises rounds x (run length + lead), where a round is one wave of
+// `slots` resident workgroups over tiles x ceil(K / run) of them and `lead`
+// prices a run's prefetch prologue in levels; ties go to the longer run.
+inline int level_run(long long tiles, long long slots, int K, int step, int min_len, int lead) {
+    if (slots <= 0) slots = 2048;
+    const int top = (K + step - 1) / step * step;
+    int best_kc = top;
+    long long best = -1;
+    for (int kc = std::min(top, (min_len + step - 1) / step * step); kc <= top; kc += step) {
+        const long long wgs = tiles * ((K + kc - 1) / kc);
+        const long long cost = (wgs + slots - 1) / slots * (kc + lead);
+        if (best < 0 || cost <= best) {
+            best = cost;
+            best_kc = kc;
+        }
+    }
+    return best_kc;
+}
 
 // Forward mode (tangent) of the fused program.  u and du at interior
 // origins with a halo of at least 2; every other field at its interior
