@@ -2,8 +2,10 @@
 // L = sum over the interior of w * x, with the limiter decisions of the
 // forward pass frozen (their derivative is taken as zero).
 //
-// Three launches on one stream:
-//   1. hdiff recomputes h (compute type) into scratch;
+// Three launches on one stream (two with FP32 or bfloat16 storage, where the
+// column kernel evaluates h itself from an LDS tile of u during its
+// elimination sweep and keeps it in LDS):
+//   1. hdiff recomputes h (compute type) into scratch (FP64 storage);
 //   2. k_vadv_adjoint, one lane per column: the transposed Thomas solve
 //      lam = T^-T w (double precision), then, walking down the column, the
 //      adjoint of the flux-form right-hand side
@@ -49,7 +51,11 @@ struct AdjArgs {
 // gc(k) = -lam(k) x(k+1).  A half with fewer than KH levels starts with
 // identity padding rows so the elimination loop has no run-time guards.
 // ---------------------------------------------------------------------------
-template <class T, int TJ, int PF, int KH, bool MATRIX>
+// FUSEH: h = hdiff(u, coeff) is evaluated here during the elimination sweep
+// (which visits the levels in the forward kernel's order) from a u tile
+// staged in LDS per level, and kept in LDS for the outward walk, instead of
+// being read from a separately computed scratch field.
+template <class T, int TJ, int PF, int KH, bool MATRIX, bool FUSEH>
 __global__ __launch_bounds__(128 * TJ) __attribute__((amdgpu_waves_per_eu(2, 8))) void
 k_vadv_adjoint(AdjArgs p, int nbi) {
 #pragma clang fp contract(off)
@@ -57,9 +63,14 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
     using C = typename S::C;
     using IO = BufIO<T>;
     using IOC = BufIO<C>;
+    using R = typename IO::R;
     constexpr int NH = 64 * TJ;
     constexpr uint32_t ES = sizeof(T), EC = sizeof(C);
+    constexpr int PI = 68, PJ = TJ + 4, MR = PJ / TJ, TILE = PJ * PI + 64;
+    static_assert(PJ % TJ == 0, "tile rows must split evenly over the lanes");
     __shared__ double2 xch[2 * NH];
+    __shared__ C utile[FUSEH ? 2 * 2 * TILE : 1];
+    __shared__ C hs[FUSEH ? KH * 2 * NH : 1];  // h of step s (local level s - shift), per lane
 
     const int tid = threadIdx.x;
     const int half = __builtin_amdgcn_readfirstlane(tid >= NH ? 1 : 0);
@@ -100,9 +111,35 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
         return static_cast<uint32_t>(min(max(k, 0), K - 1));
     };
 
+    // FUSEH: u tile of the forward kernel's layout, element (r, c) holding
+    // u(i0 - 2 + c, j0 - 2 + r), u addressed from its cell (-2, -2, 0); loads
+    // past the ring are clamped onto valid cells (never read by an active lane).
+    const int i0 = (tile % nbi) * 64, j0 = (tile / nbi) * TJ;
+    const auto ru = make_rsrc(FUSEH ? static_cast<const T *>(p.u) - 2 - 2 * p.sj : nullptr,
+                              FUSEH ? static_cast<uint32_t>(((I + 3) + static_cast<size_t>(J + 3) * p.sj +
+                                                             static_cast<size_t>(K - 1) * p.sk + 1) * ES)
+                                    : 0u);
+    const auto rcf = make_rsrc(p.coeff, FUSEH ? tbytes : 0u);
+    uint32_t vmain[MR];
+    int lmain[MR];
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+        const int r = tj + m * TJ;
+        vmain[m] = static_cast<uint32_t>(min(gi, I + 1) + 2 + (min(j0 - 2 + r, J + 1) + 2) * p.sj) * ES;
+        lmain[m] = r * PI + ti + 2;
+    }
+    const bool side_wave = tj == 0;
+    const int sr = min(l >> 2, PJ - 1), sq = l & 3;
+    const int sc = sq < 2 ? sq : sq + 64;
+    const uint32_t vside =
+        static_cast<uint32_t>(min(i0 - 2 + sc, I + 1) + 2 + (min(j0 - 2 + sr, J + 1) + 2) * p.sj) * ES;
+    const int lside = l < 4 * PJ ? sr * PI + sc : PJ * PI + ti;
+
     // Elimination: ring of the next PF steps' b, w, lower (of level t, used at
-    // step t + 1) and upper (of level t + 1).
+    // step t + 1) and upper (of level t + 1); with FUSEH also the u tile and
+    // coeff of level t (raw stored bits).
     double rbv[PF], rwv[PF], rlov[PF], rupv[PF];
+    R rum[PF][FUSEH ? MR : 1], rus[PF], rcv[PF];
     auto load = [&](int q, int s) {
         const int t = max(s - shift, 0);
         const uint32_t o = clampk(t) * skt, o1 = clampk(t + 1) * skt;
@@ -110,6 +147,12 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
         rwv[q] = IO::template load<2>(rw, vt, o);
         rlov[q] = IO::template load<2>(rlo, vt, o);
         rupv[q] = IO::template load<2>(rup, vt, o1);
+        if constexpr (FUSEH) {
+#pragma unroll
+            for (int m = 0; m < MR; ++m) rum[q][m] = IO::load_raw(ru, vmain[m], o);
+            if (side_wave) rus[q] = IO::load_raw(ru, vside, o);
+            rcv[q] = IO::template load_raw<2>(rcf, vt, o);
+        }
     };
 #pragma unroll
     for (int q = 0; q < PF && q < KH; ++q) load(q, q);
@@ -123,7 +166,19 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
         double bt = rbv[q], wt = rwv[q], upt = rupv[q];
         const double lot = first ? 0.0 : lo_carry;  // the far-end row has no lower neighbour
         lo_carry = rlov[q];
+        C cf = C(0);
+        C *tb = &utile[FUSEH ? (half * 2 + (s & 1)) * TILE : 0];
+        if constexpr (FUSEH) {
+#pragma unroll
+            for (int m = 0; m < MR; ++m) tb[lmain[m]] = IO::cvt(rum[q][m]);
+            if (side_wave) tb[lside] = IO::cvt(rus[q]);
+            cf = IO::cvt(rcv[q]);
+        }
         if (s + PF < KH) load(q, s + PF);
+        if constexpr (FUSEH) {
+            __syncthreads();
+            hs[s * 2 * NH + tid] = hdiff_point<C, PI>(tb + (tj + 2) * PI + ti + 2, cf);
+        }
         // The interface row's upper belongs to the other half's first level;
         // with an empty other half (K = 1) it is never used.
         if (pad) {
@@ -168,9 +223,11 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
     auto wload = [&](int q, int t) {
         const uint32_t k = clampk(t);
         rwc_[q] = IO::template load<2>(rwc, vt, k * skt);
-        rh_[q] = IOC::load(rh, vc, k * skc);
+        rh_[q] = FUSEH ? 0.0 : static_cast<double>(IOC::load(rh, vc, k * skc));
         rx_[q] = MATRIX ? static_cast<double>(IO::template load<2>(rx, vt, k * skt)) : 0.0;
     };
+    // h of step index st (FUSEH: from LDS; the other half's via its lane xo).
+    const int xo = half ? l : NH + l;
     // Slot q holds local level (step index q) - shift, step index = static.
     // Walk order: the interface level (step KH - 1), then steps KH - 2, ...
 #pragma unroll
@@ -181,12 +238,12 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
     if (other) {
         const uint32_t k = clampk(nsteps);
         wc_in = IO::template load<2>(rwc, vt, k * skt);
-        h_in = IOC::load(rh, vc, k * skc);
+        h_in = FUSEH ? static_cast<double>(hs[(KH - 1) * 2 * NH + xo]) : static_cast<double>(IOC::load(rh, vc, k * skc));
         if constexpr (MATRIX) x_in = IO::template load<2>(rx, vt, k * skt);
     }
     bool has_in = other;
     double lam = half ? x_hi : x_lo;  // lam of the current level
-    double wc_t = rwc_[0], h_t = rh_[0], x_t = rx_[0];
+    double wc_t = rwc_[0], h_t = FUSEH ? static_cast<double>(hs[(KH - 1) * 2 * NH + tid]) : rh_[0], x_t = rx_[0];
     if (KH - 1 - WR >= 0) wload(0, KH - 1 - WR - shift);
     double fh_in = 0.0, wb_in = 0.0, hb_in = 0.0;  // face between the current level and "in"
     if (has_in) {
@@ -203,7 +260,8 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
             const int so = st > 0 ? st - 1 : 0;
             const int q = (KH - 1 - so) % WR;
             const double lam_o = has_out ? fmadd(-P[so], lam, D[so]) : 0.0;
-            const double wc_o = rwc_[q], h_o = rh_[q], x_o = rx_[q];
+            const double wc_o = rwc_[q], x_o = rx_[q];
+            const double h_o = FUSEH ? static_cast<double>(hs[so * 2 * NH + tid]) : rh_[q];
             double g = lam, gw = 0.0, fh_o = 0.0, wb_o = 0.0, hb_o = 0.0;
             if (has_in) {
                 g = fmadd(0.5 * fh_in, wb_in, g);
@@ -424,16 +482,16 @@ size_t adjoint_scratch_bytes(int dtype, int sk, int K) {
     return 2 * (static_cast<size_t>(sk) * K * cs + 256);
 }
 
-template <class T, int KH, int WPE_UNUSED = 2>
+template <class T, int KH, bool FUSEH>
 static void launch_vadv_adjoint_t(const AdjArgs &a, hipStream_t st) {
     constexpr int TJ = 2, PF = 4;
     const int nbi = (a.I + 63) / 64, nbj = (a.J + TJ - 1) / TJ;
     if (a.ga || a.gb || a.gc)
-        hipLaunchKernelGGL((k_vadv_adjoint<T, TJ, PF, KH, true>), dim3(nbi * nbj), dim3(128 * TJ), 0, st, a,
-                           nbi);
+        hipLaunchKernelGGL((k_vadv_adjoint<T, TJ, PF, KH, true, FUSEH>), dim3(nbi * nbj), dim3(128 * TJ), 0, st,
+                           a, nbi);
     else
-        hipLaunchKernelGGL((k_vadv_adjoint<T, TJ, PF, KH, false>), dim3(nbi * nbj), dim3(128 * TJ), 0, st, a,
-                           nbi);
+        hipLaunchKernelGGL((k_vadv_adjoint<T, TJ, PF, KH, false, FUSEH>), dim3(nbi * nbj), dim3(128 * TJ), 0,
+                           st, a, nbi);
 }
 
 template <class T>
@@ -442,20 +500,25 @@ static hipError_t adjoint_run(AdjArgs a, void *scratch, hipStream_t st) {
     const size_t plane = (static_cast<size_t>(a.sk) * a.K * sizeof(C) + 255) / 256 * 256;
     a.h = scratch;
     a.gh = static_cast<char *>(scratch) + plane;
-    HdiffArgs hd{};
-    hd.u = a.u;
-    hd.coeff = a.coeff;
-    hd.out = a.h;
-    hd.I = a.I; hd.J = a.J; hd.K = a.K; hd.sj = a.sj; hd.sk = a.sk;
-    hipError_t e = launch_hdiff_compute(std::is_same<T, double>::value ? DT_F64
-                                        : std::is_same<T, float>::value ? DT_F32 : DT_BF16,
-                                        hd, st);
-    if (e != hipSuccess) return e;
+    // FP32 and bfloat16 storage evaluate h inside the column kernel (FUSEH,
+    // h held in LDS); FP64's h would take twice the LDS, so it is computed by
+    // the hdiff kernel into scratch first.
+    constexpr bool FUSEH = !std::is_same<T, double>::value;
+    hipError_t e = hipSuccess;
+    if constexpr (!FUSEH) {
+        HdiffArgs hd{};
+        hd.u = a.u;
+        hd.coeff = a.coeff;
+        hd.out = a.h;
+        hd.I = a.I; hd.J = a.J; hd.K = a.K; hd.sj = a.sj; hd.sk = a.sk;
+        e = launch_hdiff_compute(DT_F64, hd, st);
+        if (e != hipSuccess) return e;
+    }
     const int m = (a.K + 1) / 2;  // levels of the longer half
-    if (m <= 16) launch_vadv_adjoint_t<T, 16>(a, st);
-    else if (m <= 32) launch_vadv_adjoint_t<T, 32>(a, st);
-    else if (m <= 40) launch_vadv_adjoint_t<T, 40>(a, st);
-    else launch_vadv_adjoint_t<T, 48>(a, st);
+    if (m <= 16) launch_vadv_adjoint_t<T, 16, FUSEH>(a, st);
+    else if (m <= 32) launch_vadv_adjoint_t<T, 32, FUSEH>(a, st);
+    else if (m <= 40) launch_vadv_adjoint_t<T, 40, FUSEH>(a, st);
+    else launch_vadv_adjoint_t<T, 48, FUSEH>(a, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     // Rows per hdiff-adjoint tile: 8 (two per thread) where the staged tile
