@@ -271,6 +271,36 @@ def variant_adjoint(n=256, nk=80):
     return out
 
 
+def variant_frontend(ni=512, nj=512, nk=80):
+    """hdiff written as a stencil program, inlined, unrolled and compiled at
+    run time by the front end (FP32), beside the hand-written hdiff kernel."""
+    from paper_2005_13014_amd import binding as B
+    from paper_2005_13014_amd import frontend as F
+    from paper_2005_13014_amd import inputs
+    nb = 4 * (u_cells(ni, nj, nk) + 2 * ni * nj * nk)
+    sets = []
+    for q in range(n_sets_for(nb)):
+        f = inputs.fields(ni, nj, nk, 2, seed=SEED + 1 + q, storage="f32", vadv=False)
+        sets.append({"u": B.Field.from_numpy(f["u"], 2, "f32"),
+                     "coeff": B.Field.from_numpy(f["coeff"], 2, "f32"),
+                     "x": B.Field.empty(ni, nj, nk, 2, "f32", fill=0.0)})
+    out = {}
+    for unroll in (1, 2, 4):
+        k = F.compile_program(F.hdiff_program(), "f32", like=sets[0]["u"], unroll=unroll)
+
+        def fn(g, k=k):
+            k({"u": g["u"], "coeff": g["coeff"]}, {"out": g["x"]})
+        w, kt = time_calls(fn, sets, 20, 3)
+        k.close()
+        out["generated_unroll%d" % unroll] = {"ms": w, "algorithmic_GBs": nb / (kt * 1e-3) / 1e9}
+
+    def hand(g):
+        B.stencil_hdiff(g["u"], g["coeff"], g["x"])
+    w, kt = time_calls(hand, sets, 20, 3)
+    out["hand_written_inline"] = {"ms": w, "algorithmic_GBs": nb / (kt * 1e-3) / 1e9}
+    return out
+
+
 def variant_jvp(n=256, nk=80):
     """Forward mode (tangent in all six inputs) at the reverse mode's size."""
     import numpy as np
@@ -491,7 +521,7 @@ def main():
                     help="only the headline measurement (no variants, no CPU baseline)")
     ap.add_argument("--with-copy", action="store_true",
                     help="with --quick: also run the copy probe (counter calibration)")
-    ap.add_argument("--only", choices=["timestep", "timestep_implicit", "adjoint", "jvp"],
+    ap.add_argument("--only", choices=["timestep", "timestep_implicit", "adjoint", "jvp", "frontend"],
                     help="run only this variant and print its figures (for profiling)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write the profile summaries under profiles/ from rocprofv3 output in DIR "
@@ -523,7 +553,7 @@ def main():
     log("device:", dev.name, "CUs:", dev.multi_processor_count)
     if args.only:
         fn = {"timestep": variant_program, "timestep_implicit": lambda: variant_program(implicit=True),
-              "adjoint": variant_adjoint, "jvp": variant_jvp}[args.only]
+              "adjoint": variant_adjoint, "jvp": variant_jvp, "frontend": variant_frontend}[args.only]
         print(json.dumps({"variant": args.only, "result": fn()}), flush=True)
         return
 
@@ -604,6 +634,9 @@ def main():
     torch.cuda.empty_cache()
     log("variant forward mode 256x256x80")
     variants["jvp_256x256x80"] = variant_jvp()
+    torch.cuda.empty_cache()
+    log("variant front end: generated hdiff 512x512x80")
+    variants["frontend_hdiff_f32_512x512x80"] = variant_frontend()
     result["variants"] = variants
     log("cpu baseline (oracle)")
     result["cpu_baseline"] = cpu_baseline(ni, nj, nk)

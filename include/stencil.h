@@ -254,6 +254,27 @@ enum {
  * is written on its interior.  Uses library-owned device scratch. */
 int stencil_program_run(const stencil_program_t *prog, void *stream);
 
+/* ---- run-time compiled stencil programs ---------------------------------- */
+
+/* The stencil-program front end (Python, paper_2005_13014_amd/frontend.py)
+ * turns a program of stencil applies into one inlined, unrolled kernel whose
+ * extents and strides are compile-time constants (Sec. IV-V), as HIP source.
+ * stencil_rtc_compile builds it for gfx950 with hipRTC (the library's own
+ * code-generation flags) and returns an opaque handle owned by the caller
+ * (release with stencil_rtc_release).  source: NUL-terminated HIP source;
+ * kernel_name: its extern "C" __global__ function.  Compile errors return
+ * STENCIL_E_ARG with the compiler log in stencil_last_error(). */
+int stencil_rtc_compile(const char *source, const char *kernel_name, void **handle);
+
+/* Launches a compiled kernel on `stream`: grid[3] workgroups of block[3]
+ * threads (at most 1024), args[q] pointing at the q-th kernel argument's
+ * value (hipModuleLaunchKernel convention).  An empty grid is a no-op. */
+int stencil_rtc_launch(void *handle, const uint32_t grid[3], const uint32_t block[3], void **args,
+                       void *stream);
+
+/* Unloads a compiled kernel; NULL is a no-op. */
+int stencil_rtc_release(void *handle);
+
 /* ---- library management and measurement --------------------------------- */
 
 /* Message describing the calling thread's last nonzero return code. */

@@ -78,6 +78,10 @@ _SIGNATURES = {
     "stencil_hdiff_vadv_jvp": [_P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P, _P, _P, _P,
                                _C, _V],
     "stencil_program_run": [ctypes.POINTER(Program), _V],
+    "stencil_rtc_compile": [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)],
+    "stencil_rtc_launch": [_V, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                           ctypes.POINTER(ctypes.c_void_p), _V],
+    "stencil_rtc_release": [_V],
     "stencil_last_error": [],
     "stencil_abi_version": [],
     "stencil_shutdown": [],
@@ -250,6 +254,25 @@ def stencil_hdiff_vadv_jvp(u, coeff, wcon, a, b, c, dt, dx, x=None, du=None, dco
     _check(lib().stencil_hdiff_vadv_jvp(
         _desc(u), _desc(coeff), _desc(wcon), _desc(a), _desc(b), _desc(c), float(dt), _desc(x), _desc(du),
         _desc(dcoeff), _desc(dwcon), _desc(da), _desc(db), _desc(dc), _desc(dx), _cfg(cfg), _stream(stream)))
+
+
+def stencil_rtc_compile(source, kernel_name):
+    """Compiles generated HIP source; returns the kernel handle (an int)."""
+    h = ctypes.c_void_p()
+    _check(lib().stencil_rtc_compile(source.encode(), kernel_name.encode(), ctypes.byref(h)))
+    return h.value
+
+
+def stencil_rtc_launch(handle, grid, block, args, stream=None):
+    """args: ctypes scalars / pointers, one per kernel parameter, in order."""
+    g = (ctypes.c_uint32 * 3)(*grid)
+    b = (ctypes.c_uint32 * 3)(*block)
+    ptrs = (ctypes.c_void_p * len(args))(*[ctypes.cast(ctypes.pointer(a), ctypes.c_void_p) for a in args])
+    _check(lib().stencil_rtc_launch(ctypes.c_void_p(handle), g, b, ptrs, _stream(stream)))
+
+
+def stencil_rtc_release(handle):
+    _check(lib().stencil_rtc_release(ctypes.c_void_p(handle)))
 
 
 def stencil_program_run(prog, stream=None):

@@ -77,7 +77,7 @@ def build(force: bool = True, jobs: int | None = None, verbose: bool = False) ->
         raise RuntimeError("HIP build failed:\n" + msg)
     if todo or not os.path.exists(LIB):
         tmp = LIB + ".tmp%d" % os.getpid()
-        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lhiprtc"]
         r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
         if r.returncode != 0:
             raise RuntimeError("link failed:\n" + r.stdout[-4000:])

@@ -1,0 +1,369 @@
+"""A small stencil-program front end: the paper's method for programs beyond
+the hand-written hdiff + vadv kernels.
+
+A program is a sequence of *applies* (Sec. IV-A): each computes one value per
+grid point from neighbourhood *accesses* of program inputs or of earlier
+applies, with constant offsets in i and j (the paper's ``stencil.access`` with
+its offset vector; levels are independent here: no k offsets).  Three passes
+then produce one GPU kernel:
+
+* **shape inference** (Sec. V-B): walking back from the outputs, the region
+  each apply must be computed on and the halo each input must carry;
+* **inlining** (Sec. V-A): every access to an apply is replaced by that
+  apply's expression shifted by the access offset, so the kernel keeps no
+  temporaries and recomputes instead;
+* **unrolling** (Sec. V-A): each thread evaluates ``unroll`` consecutive
+  points in j, which exposes the subexpressions they share to the compiler.
+
+Code generation emits HIP source whose extents and strides are compile-time
+constants (the paper specialises on static shapes, Sec. IV-B) and compiles it
+at run time through the library (``stencil_rtc_compile``).  The generated
+kernel is the paper's execution model: one thread per point (times
+``unroll``), one level per workgroup layer, no synchronisation.
+
+Example (horizontal diffusion, the ``hdiffsa`` benchmark)::
+
+    prog = hdiff_program()
+    k = compile_program(prog, "f32", like=u_field, unroll=2)
+    k({"u": u, "coeff": coeff}, {"out": out})
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import binding as B
+
+# ---------------------------------------------------------------------------
+# Expressions
+# ---------------------------------------------------------------------------
+
+
+class Expr:
+    def _wrap(self, v):
+        return v if isinstance(v, Expr) else Num(float(v))
+
+    def __add__(self, o):
+        return Bin("+", self, self._wrap(o))
+
+    def __radd__(self, o):
+        return Bin("+", self._wrap(o), self)
+
+    def __sub__(self, o):
+        return Bin("-", self, self._wrap(o))
+
+    def __rsub__(self, o):
+        return Bin("-", self._wrap(o), self)
+
+    def __mul__(self, o):
+        return Bin("*", self, self._wrap(o))
+
+    def __rmul__(self, o):
+        return Bin("*", self._wrap(o), self)
+
+    def __truediv__(self, o):
+        return Bin("/", self, self._wrap(o))
+
+    def __rtruediv__(self, o):
+        return Bin("/", self._wrap(o), self)
+
+    def __neg__(self):
+        return Neg(self)
+
+    def __gt__(self, o):
+        return Cmp(">", self, self._wrap(o))
+
+    def __lt__(self, o):
+        return Cmp("<", self, self._wrap(o))
+
+    def __ge__(self, o):
+        return Cmp(">=", self, self._wrap(o))
+
+    def __le__(self, o):
+        return Cmp("<=", self, self._wrap(o))
+
+
+class Num(Expr):
+    def __init__(self, value):
+        self.value = float(value)
+
+
+class Acc(Expr):
+    """Access of ``src`` (an Input or an Apply) at offset (di, dj)."""
+
+    def __init__(self, src, di, dj):
+        self.src, self.di, self.dj = src, int(di), int(dj)
+
+
+class Bin(Expr):
+    def __init__(self, op, a, b):
+        self.op, self.a, self.b = op, a, b
+
+
+class Neg(Expr):
+    def __init__(self, a):
+        self.a = a
+
+
+class Cmp(Expr):
+    def __init__(self, op, a, b):
+        self.op, self.a, self.b = op, a, b
+
+
+class Sel(Expr):
+    def __init__(self, c, a, b):
+        self.c, self.a, self.b = c, a, b
+
+
+def select(cond, a, b):
+    """cond ? a : b, evaluated branch-free in the generated code."""
+    w = Expr()._wrap
+    return Sel(cond, w(a), w(b))
+
+
+class _Source:
+    def __getitem__(self, off):
+        di, dj = off
+        return Acc(self, di, dj)
+
+
+class Input(_Source):
+    def __init__(self, name):
+        self.name = name
+
+
+class Apply(_Source):
+    def __init__(self, name, body):
+        self.name, self.body = name, body
+
+
+class Program:
+    """Inputs, applies in definition order (each may read inputs and earlier
+    applies) and the applies that are outputs."""
+
+    def __init__(self):
+        self.inputs, self.applies, self.outputs = [], [], []
+
+    def input(self, name):
+        self._fresh(name)
+        f = Input(name)
+        self.inputs.append(f)
+        return f
+
+    def apply(self, name, body):
+        self._fresh(name)
+        if not isinstance(body, Expr):
+            body = Num(body)
+        for a in _accesses(body):
+            if a.src not in self.inputs and a.src not in self.applies:
+                raise ValueError("apply %r reads %r, which is not defined before it" % (name, a.src.name))
+        ap = Apply(name, body)
+        self.applies.append(ap)
+        return ap
+
+    def output(self, *applies):
+        for a in applies:
+            if a not in self.applies:
+                raise ValueError("outputs must be applies of this program")
+            self.outputs.append(a)
+
+    def _fresh(self, name):
+        if not name.isidentifier() or any(x.name == name for x in self.inputs + self.applies):
+            raise ValueError("names must be fresh identifiers (%r)" % name)
+
+
+def _children(e):
+    if isinstance(e, (Bin, Cmp)):
+        return (e.a, e.b)
+    if isinstance(e, Neg):
+        return (e.a,)
+    if isinstance(e, Sel):
+        return (e.c, e.a, e.b)
+    return ()
+
+
+def _accesses(e):
+    out, stack = [], [e]
+    while stack:
+        x = stack.pop()
+        if isinstance(x, Acc):
+            out.append(x)
+        stack.extend(_children(x))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Shape inference (Sec. V-B)
+# ---------------------------------------------------------------------------
+
+
+def infer_shapes(prog):
+    """Returns (growth, halo): growth[apply name] = (west, east, south, north),
+    the cells beyond the interior on each side on which the apply is needed;
+    halo[input name] the same for each input, i.e. the halo it must carry."""
+    if not prog.outputs:
+        raise ValueError("the program has no outputs")
+    grow = {a.name: None for a in prog.applies}
+    halo = {f.name: (0, 0, 0, 0) for f in prog.inputs}
+    for o in prog.outputs:
+        grow[o.name] = (0, 0, 0, 0)
+    for ap in reversed(prog.applies):
+        g = grow[ap.name]
+        if g is None:
+            continue  # not needed by any output
+        for a in _accesses(ap.body):
+            w, e, s, n = g
+            need = (w - a.di, e + a.di, s - a.dj, n + a.dj)
+            tbl = halo if isinstance(a.src, Input) else grow
+            old = tbl[a.src.name] or (0, 0, 0, 0)
+            tbl[a.src.name] = tuple(max(0, x, y) for x, y in zip(old, need))
+    return grow, halo
+
+
+# ---------------------------------------------------------------------------
+# Inlining (Sec. V-A)
+# ---------------------------------------------------------------------------
+
+
+def inline(e, di=0, dj=0):
+    """The expression with every access to an apply replaced by that apply's
+    expression shifted by the access offset (and the whole shifted by
+    (di, dj)): only input accesses remain."""
+    if isinstance(e, Acc):
+        if isinstance(e.src, Apply):
+            return inline(e.src.body, di + e.di, dj + e.dj)
+        return Acc(e.src, e.di + di, e.dj + dj)
+    if isinstance(e, Num):
+        return e
+    if isinstance(e, Bin):
+        return Bin(e.op, inline(e.a, di, dj), inline(e.b, di, dj))
+    if isinstance(e, Cmp):
+        return Cmp(e.op, inline(e.a, di, dj), inline(e.b, di, dj))
+    if isinstance(e, Neg):
+        return Neg(inline(e.a, di, dj))
+    if isinstance(e, Sel):
+        return Sel(inline(e.c, di, dj), inline(e.a, di, dj), inline(e.b, di, dj))
+    raise TypeError(type(e))
+
+
+# ---------------------------------------------------------------------------
+# Code generation
+# ---------------------------------------------------------------------------
+
+_CTYPE = {"f64": "double", "f32": "float"}
+
+
+def _emit(e, ctype, load):
+    if isinstance(e, Num):
+        v = repr(e.value)
+        return "%s(%s)" % (ctype, v)
+    if isinstance(e, Acc):
+        return load(e.src.name, e.di, e.dj)
+    if isinstance(e, Bin):
+        return "(%s %s %s)" % (_emit(e.a, ctype, load), e.op, _emit(e.b, ctype, load))
+    if isinstance(e, Cmp):
+        return "(%s %s %s)" % (_emit(e.a, ctype, load), e.op, _emit(e.b, ctype, load))
+    if isinstance(e, Neg):
+        return "(-%s)" % _emit(e.a, ctype, load)
+    if isinstance(e, Sel):
+        return "(%s ? %s : %s)" % (_emit(e.c, ctype, load), _emit(e.a, ctype, load), _emit(e.b, ctype, load))
+    raise TypeError(type(e))
+
+
+TI, TJ = 64, 4  # threads per workgroup in i and j (256 lanes)
+
+
+def generate(prog, dtype, ni, nj, nk, sj, sk, unroll=1, name="stencil_program"):
+    """HIP source of the inlined, unrolled program specialised on the extents
+    (ni, nj, nk) and the strides (sj, sk) every field shares.  Kernel
+    parameters: one pointer per input (interior origin), then one per output,
+    in program order."""
+    if dtype not in _CTYPE:
+        raise ValueError("dtype must be f64 or f32")
+    if unroll not in (1, 2, 4, 8):
+        raise ValueError("unroll must be 1, 2, 4 or 8")
+    infer_shapes(prog)
+    ct = _CTYPE[dtype]
+    params = ["const %s *__restrict__ in_%s" % (ct, f.name) for f in prog.inputs]
+    params += ["%s *__restrict__ out_%s" % (ct, o.name) for o in prog.outputs]
+    lines = [
+        "// Generated by the stencil front end: %d applies inlined into one kernel," % len(prog.applies),
+        "// %d point(s) per thread along j; extents and strides are compile-time." % unroll,
+        'extern "C" __global__ __launch_bounds__(%d) void %s(%s) {' % (TI * TJ, name, ", ".join(params)),
+        "    constexpr int I = %d, J = %d, K = %d;" % (ni, nj, nk),
+        "    constexpr long long SJ = %d, SK = %d;" % (sj, sk),
+        "    const int i = blockIdx.x * %d + (threadIdx.x & %d);" % (TI, TI - 1),
+        "    const int j0 = (blockIdx.y * %d + (threadIdx.x >> %d)) * %d;" % (TJ, TI.bit_length() - 1, unroll),
+        "    const int k = blockIdx.z;",
+        "    if (i >= I || k >= K) return;",
+        "    const long long o0 = i + j0 * SJ + k * SK;",
+    ]
+    for u in range(unroll):
+        def load(fname, di, dj, u=u):
+            return "in_%s[o0 + %d + %d * SJ]" % (fname, di, dj + u)
+        lines.append("    if (j0 + %d < J) {" % u)
+        for o in prog.outputs:
+            lines.append("        out_%s[o0 + %d * SJ] = %s;" % (o.name, u, _emit(inline(o.body), ct, load)))
+        lines.append("    }")
+    lines.append("}")
+    return "\n".join(lines) + "\n"
+
+
+class CompiledProgram:
+    """A program compiled for one shape and storage type; call it with dicts
+    of Fields (inputs and outputs by name).  Checks that every field has the
+    shape, strides and dtype it was compiled for and that each input carries
+    the halo shape inference derived."""
+
+    def __init__(self, prog, dtype, ni, nj, nk, sj, sk, unroll=1):
+        self.prog, self.dtype, self.unroll = prog, dtype, unroll
+        self.shape, self.strides = (ni, nj, nk), (sj, sk)
+        _, self.halo = infer_shapes(prog)
+        self.source = generate(prog, dtype, ni, nj, nk, sj, sk, unroll)
+        self.handle = B.stencil_rtc_compile(self.source, "stencil_program")
+
+    def __call__(self, inputs, outputs, stream=None):
+        ni, nj, nk = self.shape
+        args = []
+        for f in self.prog.inputs:
+            fld = inputs[f.name]
+            self._check(fld, f.name)
+            w, e, s, n = self.halo[f.name]
+            if max(w, e) > fld.hi or max(s, n) > fld.hj:
+                raise ValueError("input %s needs halo (%d, %d) in (i, j), has (%d, %d)"
+                                 % (f.name, max(w, e), max(s, n), fld.hi, fld.hj))
+            args.append(ctypes.c_void_p(fld.data_ptr()))
+        for o in self.prog.outputs:
+            fld = outputs[o.name]
+            self._check(fld, o.name)
+            args.append(ctypes.c_void_p(fld.data_ptr()))
+        grid = ((ni + TI - 1) // TI, (nj + TJ * self.unroll - 1) // (TJ * self.unroll), nk)
+        B.stencil_rtc_launch(self.handle, grid, (TI * TJ, 1, 1), args, stream)
+
+    def _check(self, fld, name):
+        if (fld.ni, fld.nj, fld.nk) != self.shape or (fld.sj, fld.sk) != self.strides or fld.dtype != self.dtype:
+            raise ValueError("field %s does not match the shape, strides or dtype compiled for" % name)
+
+    def close(self):
+        if self.handle:
+            B.stencil_rtc_release(self.handle)
+            self.handle = None
+
+
+def compile_program(prog, dtype, like, unroll=1):
+    """Compiles `prog` for fields laid out like the Field `like`."""
+    return CompiledProgram(prog, dtype, like.ni, like.nj, like.nk, like.sj, like.sk, unroll)
+
+
+def hdiff_program():
+    """Horizontal diffusion written as a stencil program: Laplacian, limited
+    fluxes in i and j, update (the operator definitions of the fused kernel)."""
+    p = Program()
+    u, coeff = p.input("u"), p.input("coeff")
+    lap = p.apply("lap", 4.0 * u[0, 0] - u[1, 0] - u[-1, 0] - u[0, 1] - u[0, -1])
+    fx = lap[1, 0] - lap[0, 0]
+    flx = p.apply("flx", select(fx * (u[1, 0] - u[0, 0]) > 0.0, 0.0, fx))
+    fy = lap[0, 1] - lap[0, 0]
+    fly = p.apply("fly", select(fy * (u[0, 1] - u[0, 0]) > 0.0, 0.0, fy))
+    out = p.apply("out", u[0, 0] - coeff[0, 0] * (flx[0, 0] - flx[-1, 0] + fly[0, 0] - fly[0, -1]))
+    p.output(out)
+    return p
