@@ -285,14 +285,16 @@ def variant_frontend(ni=512, nj=512, nk=80):
                      "coeff": B.Field.from_numpy(f["coeff"], 2, "f32"),
                      "x": B.Field.empty(ni, nj, nk, 2, "f32", fill=0.0)})
     out = {}
-    for unroll in (1, 2, 4):
-        k = F.compile_program(F.hdiff_program(), "f32", like=sets[0]["u"], unroll=unroll)
+    for tiled in (False, True):
+        for unroll in (1, 2, 4):
+            k = F.compile_program(F.hdiff_program(), "f32", like=sets[0]["u"], unroll=unroll, tiled=tiled)
 
-        def fn(g, k=k):
-            k({"u": g["u"], "coeff": g["coeff"]}, {"out": g["x"]})
-        w, kt = time_calls(fn, sets, 20, 3)
-        k.close()
-        out["generated_unroll%d" % unroll] = {"ms": w, "algorithmic_GBs": nb / (kt * 1e-3) / 1e9}
+            def fn(g, k=k):
+                k({"u": g["u"], "coeff": g["coeff"]}, {"out": g["x"]})
+            w, kt = time_calls(fn, sets, 20, 3)
+            k.close()
+            out["generated%s_unroll%d" % ("_tiled" if tiled else "", unroll)] = {
+                "ms": w, "algorithmic_GBs": nb / (kt * 1e-3) / 1e9}
 
     def hand(g):
         B.stencil_hdiff(g["u"], g["coeff"], g["x"])

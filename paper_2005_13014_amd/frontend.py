@@ -17,9 +17,11 @@ then produce one GPU kernel:
 
 Code generation emits HIP source whose extents and strides are compile-time
 constants (the paper specialises on static shapes, Sec. IV-B) and compiles it
-at run time through the library (``stencil_rtc_compile``).  The generated
-kernel is the paper's execution model: one thread per point (times
-``unroll``), one level per workgroup layer, no synchronisation.
+at run time through the library (``stencil_rtc_compile``).  By default the
+generated kernel is the paper's execution model: one thread per point (times
+``unroll``), one level per workgroup layer, no synchronisation; ``tiled``
+stages the inputs that are read at offsets in LDS over the halo shape
+inference derived and marches each workgroup over a run of levels.
 
 Example (horizontal diffusion, the ``hdiffsa`` benchmark)::
 
@@ -272,15 +274,17 @@ def _emit(e, ctype, load):
 TI, TJ = 64, 4  # threads per workgroup in i and j (256 lanes)
 
 
-def generate(prog, dtype, ni, nj, nk, sj, sk, unroll=1, name="stencil_program"):
+def generate(prog, dtype, ni, nj, nk, sj, sk, unroll=1, name="stencil_program", tiled=False, run=1):
     """HIP source of the inlined, unrolled program specialised on the extents
     (ni, nj, nk) and the strides (sj, sk) every field shares.  Kernel
     parameters: one pointer per input (interior origin), then one per output,
-    in program order."""
+    in program order.  tiled: see generate_tiled."""
     if dtype not in _CTYPE:
         raise ValueError("dtype must be f64 or f32")
     if unroll not in (1, 2, 4, 8):
         raise ValueError("unroll must be 1, 2, 4 or 8")
+    if tiled:
+        return generate_tiled(prog, dtype, ni, nj, nk, sj, sk, unroll, name, run)
     infer_shapes(prog)
     ct = _CTYPE[dtype]
     params = ["const %s *__restrict__ in_%s" % (ct, f.name) for f in prog.inputs]
@@ -308,17 +312,122 @@ def generate(prog, dtype, ni, nj, nk, sj, sk, unroll=1, name="stencil_program"):
     return "\n".join(lines) + "\n"
 
 
+PF_TILED = 4  # levels in flight in the tiled form (even: the LDS tile alternates)
+
+
+def generate_tiled(prog, dtype, ni, nj, nk, sj, sk, unroll, name, run):
+    """Tiled form: a workgroup owns a 64 x (4 unroll) tile and marches over
+    `run` consecutive levels.  Every input that is read at an offset is staged
+    in LDS over the tile grown by the halo shape inference derived for it
+    (loads outside the input's own halo are clamped onto valid cells: no point
+    of the interior reads them); inputs read only at offset 0 are read at the
+    thread's points.  The global loads of the next PF_TILED levels sit in a
+    register ring, the LDS tile is double buffered, and one barrier closes
+    each level."""
+    _, halo = infer_shapes(prog)
+    ct = _CTYPE[dtype]
+    rj, nthr = TJ * unroll, TI * TJ
+    staged = [f for f in prog.inputs if any(halo[f.name])]
+    direct = [f for f in prog.inputs if not any(halo[f.name])]
+    params = ["const %s *__restrict__ in_%s" % (ct, f.name) for f in prog.inputs]
+    params += ["%s *__restrict__ out_%s" % (ct, o.name) for o in prog.outputs]
+    L = [
+        "// Generated by the stencil front end (tiled): %d applies inlined into one kernel," % len(prog.applies),
+        "// %d point(s) per thread along j, LDS-staged inputs, %d level(s) per workgroup," % (unroll, run),
+        "// loads %d levels ahead." % PF_TILED,
+        'extern "C" __global__ __launch_bounds__(%d) void %s(%s) {' % (nthr, name, ", ".join(params)),
+        "    constexpr int I = %d, J = %d, K = %d, RUN = %d, PF = %d, UJ = %d;" % (ni, nj, nk, run, PF_TILED, unroll),
+        "    constexpr long long SJ = %d, SK = %d;" % (sj, sk),
+        "    const int tx = threadIdx.x & %d, ty = threadIdx.x >> %d;" % (TI - 1, TI.bit_length() - 1),
+        "    const int i0 = blockIdx.x * %d, jt = blockIdx.y * %d;" % (TI, rj),
+        "    const int i = i0 + tx, j0 = jt + ty * UJ;",
+        "    const int kbeg = blockIdx.z * RUN, kend = min(K, kbeg + RUN);",
+    ]
+    for f in staged:
+        n_ = f.name
+        w, e, s_, n = halo[n_]
+        L += [
+            "    // %s staged with halo (w %d, e %d, s %d, n %d)" % (n_, w, e, s_, n),
+            "    constexpr int PX_%s = %d, PY_%s = %d, W_%s = %d, S_%s = %d;" % (n_, TI + w + e, n_, rj + s_ + n, n_, w, n_, s_),
+            "    constexpr int NE_%s = (PX_%s * PY_%s + %d) / %d;" % (n_, n_, n_, nthr - 1, nthr),
+            "    __shared__ %s t_%s[2][PX_%s * PY_%s];" % (ct, n_, n_, n_),
+            "    long long o_%s[NE_%s];" % (n_, n_),
+            "    for (int q = 0; q < NE_%s; ++q) {" % n_,
+            "        const int e = min(static_cast<int>(threadIdx.x) + %d * q, PX_%s * PY_%s - 1);" % (nthr, n_, n_),
+            "        const int x = min(max(i0 - W_%s + e %% PX_%s, %d), I - 1 + %d);" % (n_, n_, -max(w, e), max(w, e)),
+            "        const int y = min(max(jt - S_%s + e / PX_%s, %d), J - 1 + %d);" % (n_, n_, -max(s_, n), max(s_, n)),
+            "        o_%s[q] = x + y * SJ;" % n_,
+            "    }",
+            "    %s r_%s[PF][NE_%s];" % (ct, n_, n_),
+        ]
+    L += [
+        "    long long od[UJ];",
+        "    for (int u = 0; u < UJ; ++u) od[u] = min(i, I - 1) + min(j0 + u, J - 1) * SJ;",
+    ]
+    for f in direct:
+        L.append("    %s r_%s[PF][UJ];" % (ct, f.name))
+    L.append("    auto load = [&](int q, int k) {")
+    L.append("        const long long ko = min(k, kend - 1) * SK;  // past the run: its last level again")
+    for f in staged:
+        L.append("        for (int n = 0; n < NE_%s; ++n) r_%s[q][n] = in_%s[ko + o_%s[n]];" % ((f.name,) * 4))
+    for f in direct:
+        L.append("        for (int u = 0; u < UJ; ++u) r_%s[q][u] = in_%s[ko + od[u]];" % (f.name, f.name))
+    L += [
+        "    };",
+        "#pragma unroll",
+        "    for (int q = 0; q < PF; ++q) load(q, kbeg + q);",
+        "    for (int kk = kbeg; kk < kend; kk += PF) {",
+        "#pragma unroll",
+        "        for (int q = 0; q < PF; ++q) {",
+        "            const int k = kk + q;",
+        "            if (k >= kend) break;",
+        "            const long long ko = k * SK;",
+    ]
+    for f in staged:
+        n_ = f.name
+        L += [
+            "            %s *tb_%s = t_%s[q & 1];" % (ct, n_, n_),
+            "            for (int n = 0; n < NE_%s; ++n)" % n_,
+            "                if (threadIdx.x + %d * n < PX_%s * PY_%s) tb_%s[threadIdx.x + %d * n] = r_%s[q][n];"
+            % (nthr, n_, n_, n_, nthr, n_),
+        ]
+    for f in direct:
+        L.append("            %s v_%s[UJ];" % (ct, f.name))
+        L.append("            for (int u = 0; u < UJ; ++u) v_%s[u] = r_%s[q][u];" % (f.name, f.name))
+    L += [
+        "            load(q, k + PF);",
+        "            __syncthreads();",
+        "            if (i < I) {",
+    ]
+    staged_names = [f.name for f in staged]
+    for u in range(unroll):
+        def load_expr(fname, di, dj, u=u):
+            if fname in staged_names:
+                return "tb_%s[(ty * UJ + %d + %d + S_%s) * PX_%s + tx + %d + W_%s]" % (
+                    fname, u, dj, fname, fname, di, fname)
+            return "v_%s[%d]" % (fname, u)
+        L.append("                if (j0 + %d < J) {" % u)
+        for o in prog.outputs:
+            L.append("                    out_%s[ko + i + (j0 + %d) * SJ] = %s;" % (o.name, u, _emit(inline(o.body), ct, load_expr)))
+        L.append("                }")
+    L += ["            }", "        }", "    }", "}"]
+    return "\n".join(L) + "\n"
+
+
 class CompiledProgram:
     """A program compiled for one shape and storage type; call it with dicts
     of Fields (inputs and outputs by name).  Checks that every field has the
     shape, strides and dtype it was compiled for and that each input carries
     the halo shape inference derived."""
 
-    def __init__(self, prog, dtype, ni, nj, nk, sj, sk, unroll=1):
-        self.prog, self.dtype, self.unroll = prog, dtype, unroll
+    def __init__(self, prog, dtype, ni, nj, nk, sj, sk, unroll=1, tiled=False):
+        self.prog, self.dtype, self.unroll, self.tiled = prog, dtype, unroll, tiled
         self.shape, self.strides = (ni, nj, nk), (sj, sk)
         _, self.halo = infer_shapes(prog)
-        self.source = generate(prog, dtype, ni, nj, nk, sj, sk, unroll)
+        # Tiled: levels per workgroup so that the launch has about 4096 workgroups.
+        tiles = ((ni + TI - 1) // TI) * ((nj + TJ * unroll - 1) // (TJ * unroll))
+        self.run = max(1, -(-nk // max(1, 4096 // max(1, tiles)))) if tiled else 1
+        self.source = generate(prog, dtype, ni, nj, nk, sj, sk, unroll, tiled=tiled, run=self.run)
         self.handle = B.stencil_rtc_compile(self.source, "stencil_program")
 
     def __call__(self, inputs, outputs, stream=None):
@@ -336,7 +445,8 @@ class CompiledProgram:
             fld = outputs[o.name]
             self._check(fld, o.name)
             args.append(ctypes.c_void_p(fld.data_ptr()))
-        grid = ((ni + TI - 1) // TI, (nj + TJ * self.unroll - 1) // (TJ * self.unroll), nk)
+        grid = ((ni + TI - 1) // TI, (nj + TJ * self.unroll - 1) // (TJ * self.unroll),
+                (nk + self.run - 1) // self.run)
         B.stencil_rtc_launch(self.handle, grid, (TI * TJ, 1, 1), args, stream)
 
     def _check(self, fld, name):
@@ -349,9 +459,11 @@ class CompiledProgram:
             self.handle = None
 
 
-def compile_program(prog, dtype, like, unroll=1):
-    """Compiles `prog` for fields laid out like the Field `like`."""
-    return CompiledProgram(prog, dtype, like.ni, like.nj, like.nk, like.sj, like.sk, unroll)
+def compile_program(prog, dtype, like, unroll=1, tiled=False):
+    """Compiles `prog` for fields laid out like the Field `like`; tiled
+    selects the LDS-staged, level-marching form (generate_tiled) over the
+    one-thread-per-point form."""
+    return CompiledProgram(prog, dtype, like.ni, like.nj, like.nk, like.sj, like.sk, unroll, tiled)
 
 
 def hdiff_program():

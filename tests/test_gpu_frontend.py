@@ -21,11 +21,11 @@ def note(*a):
     print(*a, flush=True)
 
 
-def run_hdiff(f, dtype, unroll):
+def run_hdiff(f, dtype, unroll, tiled=False):
     u = B.Field.from_numpy(f["u"], 2, dtype)
     coeff = B.Field.from_numpy(f["coeff"], 2, dtype)
     out = u.like(fill=-7.0)
-    k = F.compile_program(F.hdiff_program(), dtype, like=u, unroll=unroll)
+    k = F.compile_program(F.hdiff_program(), dtype, like=u, unroll=unroll, tiled=tiled)
     try:
         k({"u": u, "coeff": coeff}, {"out": out})
         torch.cuda.synchronize()
@@ -34,26 +34,28 @@ def run_hdiff(f, dtype, unroll):
     return out
 
 
+@pytest.mark.parametrize("tiled", [False, True])
 @pytest.mark.parametrize("unroll", [1, 2, 4])
 @pytest.mark.parametrize("shape", [(64, 64, 60), (70, 13, 5), (131, 9, 7), (3, 2, 1)])
-def test_generated_hdiff_fp64(shape, unroll):
+def test_generated_hdiff_fp64(shape, unroll, tiled):
     ni, nj, nk = shape
-    note("front end hdiff f64", shape, unroll)
+    note("front end hdiff f64", shape, unroll, tiled)
     f = inputs.fields(ni, nj, nk, 2, seed=SEED + 70, storage="f64", vadv=False)
-    out = run_hdiff(f, "f64", unroll)
+    out = run_hdiff(f, "f64", unroll, tiled)
     err = normwise(out.to_numpy(interior=True), oracle.hdiff(f["u"], 2, f["coeff"], 2))
     note("normwise %.2e" % err)
     assert err <= TOL["f64"]
     assert halo_untouched(out)
 
 
+@pytest.mark.parametrize("tiled", [False, True])
 @pytest.mark.parametrize("unroll", [1, 4])
-def test_generated_hdiff_fp32_under_its_own_masks(unroll):
+def test_generated_hdiff_fp32_under_its_own_masks(unroll, tiled):
     ni, nj, nk = 99, 17, 12
     f = inputs.fields(ni, nj, nk, 2, seed=SEED + 71, storage="f32", vadv=False)
     kx, ky = limiter_masks(f["u"], 2, "f32")
     ref = oracle.hdiff(f["u"], 2, f["coeff"], 2, force_kx=kx, force_ky=ky)
-    out = run_hdiff(f, "f32", unroll)
+    out = run_hdiff(f, "f32", unroll, tiled)
     err = normwise(out.to_numpy(interior=True), ref)
     note("front end hdiff f32 normwise %.2e" % err)
     assert err <= TOL["f32"]
@@ -76,12 +78,14 @@ def test_generated_biharmonic():
     ug = B.Field.from_numpy(f["u"], 2, "f64")
     cg = B.Field.from_numpy(f["coeff"], 2, "f64")
     og = ug.like(fill=-7.0)
-    k = F.compile_program(p, "f64", like=ug, unroll=2)
-    k({"u": ug, "c": cg}, {"out": og})
-    torch.cuda.synchronize()
-    k.close()
-    assert normwise(og.to_numpy(interior=True), ref) <= TOL["f64"]
-    assert halo_untouched(og)
+    for tiled in (False, True):
+        og.buf.fill_(-7.0)
+        k = F.compile_program(p, "f64", like=ug, unroll=2, tiled=tiled)
+        k({"u": ug, "c": cg}, {"out": og})
+        torch.cuda.synchronize()
+        k.close()
+        assert normwise(og.to_numpy(interior=True), ref) <= TOL["f64"]
+        assert halo_untouched(og)
 
 
 def test_halo_and_layout_checks():
