@@ -621,6 +621,10 @@ def main():
         log("variant", label)
         variants[label] = variant_column(ni, nj, nk, dt_, level)
         torch.cuda.empty_cache()
+    for dt_ in ("f32", "f64"):  # the configuration's other size
+        log("variant fused_%s_256x256x80" % dt_)
+        variants["fused_%s_256x256x80" % dt_] = variant_column(256, 256, 80, dt_, 0)
+        torch.cuda.empty_cache()
     variants["speedup_fused_f32_over_original_f64"] = variants["original_f64"]["ms"] / wall
     log("variant hdiff optimisation levels")
     variants["hdiff_f32_levels"] = variant_hdiff_levels(ni, nj, nk)
