@@ -319,7 +319,7 @@ int build_plan(const stencil_program_t *prog, int dtype, int tj, char *scratch, 
                 h.I = cf.ni; h.J = cf.nj; h.K = cf.nk;
                 h.sj = static_cast<int>(cf.sj); h.sk = static_cast<int>(cf.sk);
                 h.nbi = (cf.ni + 63) / 64;
-                h.nbj = (cf.nj + 3) / 4;
+                h.nbj = (cf.nj + HGRAD_ROWS - 1) / HGRAD_ROWS;
                 h.nfields = sd.nfields - f0 < BATCH_FIELDS ? sd.nfields - f0 : BATCH_FIELDS;
                 h.tile0 = tiles;
                 h.y_bytes = static_cast<uint32_t>(((cf.ni + 1) + (cf.nj + 1) * cf.sj + (cf.nk - 1) * cf.sk + 1) * es);

@@ -11,6 +11,8 @@ namespace stl {
 // z = y - beta_h ((y(i+1) - y(i-1))/2 + (y(j+1) - y(j-1))/2) - beta_v Dk y,
 // Dk y = (y(k+1) - y(k-1))/2 inside the column, y(1) - y(0) at the bottom and
 // y(K-1) - y(K-2) at the top (0 for a single level).  y carries a 1-cell halo.
+constexpr int HGRAD_ROWS = 4;  // rows of an hgrad tile, one wave each (8 measured no faster)
+
 struct HgradSub {
     const void *y[BATCH_FIELDS];  // interior origins
     void *z[BATCH_FIELDS];
@@ -25,19 +27,20 @@ struct HgradBatch {
     double beta_h, beta_v;
 };
 
-// One 64 x 4 tile of one field per workgroup, marching k.  Per level the
-// tile's y rows j0 - 1 .. j0 + 4 and its side columns i0 - 1, i0 + 64 are
+// One 64 x TR tile of one field per workgroup (one wave per row), marching k.
+// Per level the tile's y rows j0 - 1 .. j0 + TR and its side columns i0 - 1, i0 + 64 are
 // staged in LDS (each wave loads its own row, which holds its centre values;
 // waves 0 and 1 also load the rows above and below the tile, wave 2 the side
 // columns), the horizontal neighbours are read from the tile and the vertical
 // ones are kept in registers.  Loads run PF levels ahead.
-template <class T, int PF = 8>
-__global__ __launch_bounds__(256) void k_hgrad_batch(HgradBatch b) {
+template <class T, int TR = HGRAD_ROWS, int PF = 8>
+__global__ __launch_bounds__(64 * TR) void k_hgrad_batch(HgradBatch b) {
     static_assert(PF % 2 == 0, "the LDS tile alternates with the ring slot");
+    static_assert(TR >= 3 && 2 * (TR + 2) <= 64, "wave 2 stages both side columns of every tile row");
     using S = Storage<T>;
     using C = typename S::C;
     using IO = BufIO<T>;
-    constexpr int PI = 68, ROWS = 6, TILE = ROWS * PI;
+    constexpr int PI = 68, ROWS = TR + 2, TILE = ROWS * PI;
     constexpr uint32_t ES = sizeof(T);
     __shared__ C tile[2 * TILE];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -50,7 +53,7 @@ __global__ __launch_bounds__(256) void k_hgrad_batch(HgradBatch b) {
     const int tid = threadIdx.x, ti = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int I = sb.I, J = sb.J, sj = sb.sj, K = sb.K;
-    const int i0 = bi * 64, j0 = bj * 4;
+    const int i0 = bi * 64, j0 = bj * TR;
     const int gi = i0 + ti, gj = j0 + w;
     const bool active = gi < I && gj < J;
     // y is addressed from its cell (-1, -1, 0); cells are clamped into
@@ -62,12 +65,13 @@ __global__ __launch_bounds__(256) void k_hgrad_batch(HgradBatch b) {
     };
     const uint32_t v_own = voff(gi, gj);
     // Second row: wave 0 the row above the tile (tile row 0), wave 1 the row
-    // below it (tile row 5), wave 2 the side columns (lanes 0 .. 11), wave 3 none.
+    // below it (tile row TR + 1), wave 2 the side columns (lanes 0 .. 2 ROWS - 1),
+    // the other waves none.
     const int sr = ti >> 1, scol = (ti & 1) ? 65 : 0;  // side: tile row, tile column
-    const uint32_t v_two = w == 0 ? voff(gi, j0 - 1) : w == 1 ? voff(gi, j0 + 4) : voff(i0 - 1 + scol, j0 - 1 + min(sr, ROWS - 1));
+    const uint32_t v_two = w == 0 ? voff(gi, j0 - 1) : w == 1 ? voff(gi, j0 + TR) : voff(i0 - 1 + scol, j0 - 1 + min(sr, ROWS - 1));
     const bool two = w < 2 || (w == 2 && ti < 2 * ROWS);
     const int l_own = (w + 1) * PI + ti + 1;
-    const int l_two = w == 0 ? ti + 1 : w == 1 ? 5 * PI + ti + 1 : min(sr, ROWS - 1) * PI + scol;
+    const int l_two = w == 0 ? ti + 1 : w == 1 ? (TR + 1) * PI + ti + 1 : min(sr, ROWS - 1) * PI + scol;
     const uint32_t vz = static_cast<uint32_t>(min(gi, I - 1) + min(gj, J - 1) * sj) * ES;
     const uint32_t skb = static_cast<uint32_t>(sb.sk) * ES;
 
@@ -127,7 +131,7 @@ static hipError_t launch_column_batch_t(const ColumnBatch &b, int ntiles, hipStr
 
 template <class T>
 static hipError_t launch_hgrad_batch_t(const HgradBatch &b, int ntiles, hipStream_t st) {
-    hipLaunchKernelGGL((k_hgrad_batch<T>), dim3(ntiles), dim3(256), 0, st, b);
+    hipLaunchKernelGGL((k_hgrad_batch<T>), dim3(ntiles), dim3(64 * HGRAD_ROWS), 0, st, b);
     return hipGetLastError();
 }
 
