@@ -251,7 +251,29 @@ def inline(e, di=0, dj=0):
 # Code generation
 # ---------------------------------------------------------------------------
 
-_CTYPE = {"f64": "double", "f32": "float"}
+# storage type -> (element type in memory, compute type, widening load, rounding store)
+_TYPES = {
+    "f64": ("double", "double", "%s", "%s"),
+    "f32": ("float", "float", "%s", "%s"),
+    # bfloat16: the upper half of a float; loads are exact, stores round to
+    # nearest even (NaN stays NaN)
+    "bf16": ("unsigned short", "float", "bf16_load(%s)", "bf16_round(%s)"),
+}
+_CTYPE = {k: v[1] for k, v in _TYPES.items()}
+
+_BF16_HELPERS = """__device__ __forceinline__ float bf16_load(unsigned short b) {
+    return __uint_as_float(static_cast<unsigned>(b) << 16);
+}
+__device__ __forceinline__ unsigned short bf16_round(float v) {
+    const unsigned bits = __float_as_uint(v);
+    const unsigned rne = (bits + 0x7fffu + ((bits >> 16) & 1u)) >> 16;
+    return static_cast<unsigned short>((bits & 0x7fffffffu) > 0x7f800000u ? ((bits >> 16) | 0x40u) : rne);
+}
+"""
+
+
+def _prelude(dtype):
+    return _BF16_HELPERS if dtype == "bf16" else ""
 
 
 def _emit(e, ctype, load):
@@ -279,17 +301,17 @@ def generate(prog, dtype, ni, nj, nk, sj, sk, unroll=1, name="stencil_program", 
     (ni, nj, nk) and the strides (sj, sk) every field shares.  Kernel
     parameters: one pointer per input (interior origin), then one per output,
     in program order.  tiled: see generate_tiled."""
-    if dtype not in _CTYPE:
-        raise ValueError("dtype must be f64 or f32")
+    if dtype not in _TYPES:
+        raise ValueError("dtype must be f64, f32 or bf16")
     if unroll not in (1, 2, 4, 8):
         raise ValueError("unroll must be 1, 2, 4 or 8")
     if tiled:
         return generate_tiled(prog, dtype, ni, nj, nk, sj, sk, unroll, name, run)
     infer_shapes(prog)
-    ct = _CTYPE[dtype]
-    params = ["const %s *__restrict__ in_%s" % (ct, f.name) for f in prog.inputs]
-    params += ["%s *__restrict__ out_%s" % (ct, o.name) for o in prog.outputs]
-    lines = [
+    mt, ct, ld, stf = _TYPES[dtype]
+    params = ["const %s *__restrict__ in_%s" % (mt, f.name) for f in prog.inputs]
+    params += ["%s *__restrict__ out_%s" % (mt, o.name) for o in prog.outputs]
+    lines = [_prelude(dtype) +
         "// Generated by the stencil front end: %d applies inlined into one kernel," % len(prog.applies),
         "// %d point(s) per thread along j; extents and strides are compile-time." % unroll,
         'extern "C" __global__ __launch_bounds__(%d) void %s(%s) {' % (TI * TJ, name, ", ".join(params)),
@@ -303,10 +325,10 @@ def generate(prog, dtype, ni, nj, nk, sj, sk, unroll=1, name="stencil_program", 
     ]
     for u in range(unroll):
         def load(fname, di, dj, u=u):
-            return "in_%s[o0 + %d + %d * SJ]" % (fname, di, dj + u)
+            return ld % ("in_%s[o0 + %d + %d * SJ]" % (fname, di, dj + u))
         lines.append("    if (j0 + %d < J) {" % u)
         for o in prog.outputs:
-            lines.append("        out_%s[o0 + %d * SJ] = %s;" % (o.name, u, _emit(inline(o.body), ct, load)))
+            lines.append("        out_%s[o0 + %d * SJ] = %s;" % (o.name, u, stf % _emit(inline(o.body), ct, load)))
         lines.append("    }")
     lines.append("}")
     return "\n".join(lines) + "\n"
@@ -325,13 +347,13 @@ def generate_tiled(prog, dtype, ni, nj, nk, sj, sk, unroll, name, run):
     register ring, the LDS tile is double buffered, and one barrier closes
     each level."""
     _, halo = infer_shapes(prog)
-    ct = _CTYPE[dtype]
+    mt, ct, ld, stf = _TYPES[dtype]
     rj, nthr = TJ * unroll, TI * TJ
     staged = [f for f in prog.inputs if any(halo[f.name])]
     direct = [f for f in prog.inputs if not any(halo[f.name])]
-    params = ["const %s *__restrict__ in_%s" % (ct, f.name) for f in prog.inputs]
-    params += ["%s *__restrict__ out_%s" % (ct, o.name) for o in prog.outputs]
-    L = [
+    params = ["const %s *__restrict__ in_%s" % (mt, f.name) for f in prog.inputs]
+    params += ["%s *__restrict__ out_%s" % (mt, o.name) for o in prog.outputs]
+    L = [_prelude(dtype) +
         "// Generated by the stencil front end (tiled): %d applies inlined into one kernel," % len(prog.applies),
         "// %d point(s) per thread along j, LDS-staged inputs, %d level(s) per workgroup," % (unroll, run),
         "// loads %d levels ahead." % PF_TILED,
@@ -358,14 +380,14 @@ def generate_tiled(prog, dtype, ni, nj, nk, sj, sk, unroll, name, run):
             "        const int y = min(max(jt - S_%s + e / PX_%s, %d), J - 1 + %d);" % (n_, n_, -max(s_, n), max(s_, n)),
             "        o_%s[q] = x + y * SJ;" % n_,
             "    }",
-            "    %s r_%s[PF][NE_%s];" % (ct, n_, n_),
+            "    %s r_%s[PF][NE_%s];" % (mt, n_, n_),
         ]
     L += [
         "    long long od[UJ];",
         "    for (int u = 0; u < UJ; ++u) od[u] = min(i, I - 1) + min(j0 + u, J - 1) * SJ;",
     ]
     for f in direct:
-        L.append("    %s r_%s[PF][UJ];" % (ct, f.name))
+        L.append("    %s r_%s[PF][UJ];" % (mt, f.name))
     L.append("    auto load = [&](int q, int k) {")
     L.append("        const long long ko = min(k, kend - 1) * SK;  // past the run: its last level again")
     for f in staged:
@@ -388,12 +410,12 @@ def generate_tiled(prog, dtype, ni, nj, nk, sj, sk, unroll, name, run):
         L += [
             "            %s *tb_%s = t_%s[q & 1];" % (ct, n_, n_),
             "            for (int n = 0; n < NE_%s; ++n)" % n_,
-            "                if (threadIdx.x + %d * n < PX_%s * PY_%s) tb_%s[threadIdx.x + %d * n] = r_%s[q][n];"
-            % (nthr, n_, n_, n_, nthr, n_),
+            "                if (threadIdx.x + %d * n < PX_%s * PY_%s) tb_%s[threadIdx.x + %d * n] = %s;"
+            % (nthr, n_, n_, n_, nthr, ld % ("r_%s[q][n]" % n_)),
         ]
     for f in direct:
         L.append("            %s v_%s[UJ];" % (ct, f.name))
-        L.append("            for (int u = 0; u < UJ; ++u) v_%s[u] = r_%s[q][u];" % (f.name, f.name))
+        L.append("            for (int u = 0; u < UJ; ++u) v_%s[u] = %s;" % (f.name, ld % ("r_%s[q][u]" % f.name)))
     L += [
         "            load(q, k + PF);",
         "            __syncthreads();",
@@ -408,7 +430,8 @@ def generate_tiled(prog, dtype, ni, nj, nk, sj, sk, unroll, name, run):
             return "v_%s[%d]" % (fname, u)
         L.append("                if (j0 + %d < J) {" % u)
         for o in prog.outputs:
-            L.append("                    out_%s[ko + i + (j0 + %d) * SJ] = %s;" % (o.name, u, _emit(inline(o.body), ct, load_expr)))
+            L.append("                    out_%s[ko + i + (j0 + %d) * SJ] = %s;"
+                     % (o.name, u, stf % _emit(inline(o.body), ct, load_expr)))
         L.append("                }")
     L += ["            }", "        }", "    }", "}"]
     return "\n".join(L) + "\n"
@@ -421,6 +444,7 @@ class CompiledProgram:
     the halo shape inference derived."""
 
     def __init__(self, prog, dtype, ni, nj, nk, sj, sk, unroll=1, tiled=False):
+        # dtype: storage of every field, "f64", "f32" or "bf16" (FP32 arithmetic)
         self.prog, self.dtype, self.unroll, self.tiled = prog, dtype, unroll, tiled
         self.shape, self.strides = (ni, nj, nk), (sj, sk)
         _, self.halo = infer_shapes(prog)

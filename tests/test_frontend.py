@@ -148,7 +148,9 @@ def test_generated_source():
     assert "in_u" in src and "in_coeff" in src and "lap" not in src.split("{", 1)[1]  # no temporaries
     assert "double" in src and "float" not in src
     with pytest.raises(ValueError):
-        F.generate(prog, "bf16", 8, 8, 1, 12, 144)
+        F.generate(prog, "f16", 8, 8, 1, 12, 144)
+    b = F.generate(prog, "bf16", 8, 8, 1, 16, 192)
+    assert "unsigned short *__restrict__ out_out" in b and "bf16_round(" in b and "bf16_load(" in b
     with pytest.raises(ValueError):
         F.generate(prog, "f32", 8, 8, 1, 12, 144, unroll=3)
 

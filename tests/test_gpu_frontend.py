@@ -48,17 +48,19 @@ def test_generated_hdiff_fp64(shape, unroll, tiled):
     assert halo_untouched(out)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
 @pytest.mark.parametrize("tiled", [False, True])
 @pytest.mark.parametrize("unroll", [1, 4])
-def test_generated_hdiff_fp32_under_its_own_masks(unroll, tiled):
+def test_generated_hdiff_low_precision_under_its_own_masks(unroll, tiled, dtype):
     ni, nj, nk = 99, 17, 12
-    f = inputs.fields(ni, nj, nk, 2, seed=SEED + 71, storage="f32", vadv=False)
-    kx, ky = limiter_masks(f["u"], 2, "f32")
+    f = inputs.fields(ni, nj, nk, 2, seed=SEED + 71, storage=dtype, vadv=False)
+    kx, ky = limiter_masks(f["u"], 2, dtype)
     ref = oracle.hdiff(f["u"], 2, f["coeff"], 2, force_kx=kx, force_ky=ky)
-    out = run_hdiff(f, "f32", unroll, tiled)
+    out = run_hdiff(f, dtype, unroll, tiled)
     err = normwise(out.to_numpy(interior=True), ref)
-    note("front end hdiff f32 normwise %.2e" % err)
-    assert err <= TOL["f32"]
+    note("front end hdiff %s normwise %.2e" % (dtype, err))
+    assert err <= TOL[dtype]
+    assert halo_untouched(out)
 
 
 def test_generated_biharmonic():
