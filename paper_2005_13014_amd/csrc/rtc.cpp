@@ -6,7 +6,6 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,8 +26,6 @@ struct RtcKernel {
     hipModule_t module = nullptr;
     hipFunction_t function = nullptr;
 };
-
-std::mutex g_rtc_mu;
 
 }  // namespace
 
@@ -73,7 +70,7 @@ STENCIL_API int stencil_rtc_launch(void *handle, const uint32_t grid[3], const u
     if (!handle || !grid || !block || !args) return fail(STENCIL_E_NULL, "rtc_launch: NULL argument");
     const RtcKernel *k = static_cast<const RtcKernel *>(handle);
     if (!grid[0] || !grid[1] || !grid[2]) return STENCIL_OK;  // nothing to do
-    if (block[0] * block[1] * block[2] > 1024 || !block[0] || !block[1] || !block[2])
+    if (static_cast<uint64_t>(block[0]) * block[1] * block[2] > 1024 || !block[0] || !block[1] || !block[2])
         return fail(STENCIL_E_ARG, "rtc_launch: block of %u x %u x %u threads", block[0], block[1], block[2]);
     const hipError_t e = hipModuleLaunchKernel(k->function, grid[0], grid[1], grid[2], block[0], block[1],
                                                block[2], 0, static_cast<hipStream_t>(stream), args, nullptr);
@@ -83,7 +80,6 @@ STENCIL_API int stencil_rtc_launch(void *handle, const uint32_t grid[3], const u
 STENCIL_API int stencil_rtc_release(void *handle) {
     if (!handle) return STENCIL_OK;
     RtcKernel *k = static_cast<RtcKernel *>(handle);
-    std::lock_guard<std::mutex> lock(g_rtc_mu);
     const hipError_t e = hipModuleUnload(k->module);
     delete k;
     return e == hipSuccess ? STENCIL_OK : hip_fail(e, "rtc_release");

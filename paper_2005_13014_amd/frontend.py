@@ -87,6 +87,8 @@ class Expr:
 class Num(Expr):
     def __init__(self, value):
         self.value = float(value)
+        if self.value != self.value or self.value in (float("inf"), float("-inf")):
+            raise ValueError("constants must be finite (%r)" % value)
 
 
 class Acc(Expr):
@@ -455,6 +457,8 @@ class CompiledProgram:
         self.handle = B.stencil_rtc_compile(self.source, "stencil_program")
 
     def __call__(self, inputs, outputs, stream=None):
+        if not self.handle:
+            raise RuntimeError("the compiled program has been closed")
         ni, nj, nk = self.shape
         args = []
         for f in self.prog.inputs:
@@ -478,9 +482,23 @@ class CompiledProgram:
             raise ValueError("field %s does not match the shape, strides or dtype compiled for" % name)
 
     def close(self):
+        """Unloads the kernel (also on garbage collection and on leaving a
+        ``with`` block)."""
         if self.handle:
             B.stencil_rtc_release(self.handle)
             self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may be gone
+            pass
 
 
 def compile_program(prog, dtype, like, unroll=1, tiled=False):

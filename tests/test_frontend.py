@@ -92,6 +92,10 @@ def test_shape_inference_asymmetric_and_unused():
 
 
 def test_program_validation():
+    with pytest.raises(ValueError):
+        F.Num(float("nan"))
+    with pytest.raises(ValueError):
+        F.Program().input("u")[0, 0] * float("inf")
     p = F.Program()
     u = p.input("u")
     with pytest.raises(ValueError):
