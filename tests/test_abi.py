@@ -143,6 +143,21 @@ def test_jvp_argument_checks():
     assert jvp(base, dt=float("nan")) == 9
 
 
+def test_size_limits_of_the_column_kernels():
+    # 32-bit buffer offsets: fields of 2 GiB or more are refused (the fused
+    # level-INLINE call, the adjoint and the forward mode), before any launch.
+    sk = 6 * 1024 * 1024              # FP32: 95 * sk * 4 B > 2 GiB at nk = 96
+    big = [fd(origin=FAKE + q * (1 << 36), nk=96, sk=sk) for q in range(14)]
+    r = ctypes.byref
+    cfg = B.config(level=2)
+    assert B.lib().stencil_hdiff_vadv(*[r(f) for f in big[:6]], 10.0, r(big[6]), r(cfg), None) == 7
+    assert adjoint(big[:10]) == 7
+    assert jvp(big[:7]) == 7
+    # and more levels than the column buckets hold
+    deep = [fd(origin=FAKE + q * (1 << 30), nk=97) for q in range(10)]
+    assert adjoint(deep) == 7
+
+
 def test_null_descriptor_and_origin():
     u, c, o = spaced(3)
     assert hdiff(None, c, o) == 1
