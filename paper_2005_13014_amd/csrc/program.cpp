@@ -16,6 +16,7 @@
 // signature into a hipGraph that later calls replay.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -359,10 +360,12 @@ hipError_t enqueue(const Plan &plan, Variant v, hipStream_t st, bool columns_onl
     return hipSuccess;
 }
 
-// Times the column launches of each compiled variant (3 runs after a warm-up).
+// Times the column launches of each compiled variant: after one warm-up
+// launch each, five rounds that time every candidate once (interleaved, so
+// that clock and cache drift hit all of them alike); the median decides.
 int autotune(const stencil_program_t *prog, int dtype, char *scratch, hipStream_t st, Variant *best) {
     const std::vector<Variant> cands = variants_for(dtype);
-    float best_ms = 1e30f;
+    constexpr int ROUNDS = 5;
     *best = cands.front();
     hipEvent_t e0, e1;
     hipError_t he = hipEventCreate(&e0);
@@ -372,24 +375,35 @@ int autotune(const stencil_program_t *prog, int dtype, char *scratch, hipStream_
         hipEventDestroy(e0);
         return hip_fail(he, "hipEventCreate");
     }
-    int rc = STENCIL_OK;
-    for (const Variant &v : cands) {
-        Plan p;
-        build_plan(prog, dtype, v.tj, scratch, &p);
-        hipError_t e = enqueue(p, v, st, true);
-        if (e == hipSuccess) e = hipEventRecord(e0, st);
-        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = enqueue(p, v, st, true);
-        if (e == hipSuccess) e = hipEventRecord(e1, st);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-            rc = hip_fail(e, "autotune");
-            break;
+    std::vector<Plan> plans(cands.size());
+    std::vector<std::vector<float>> ms(cands.size());
+    hipError_t e = hipSuccess;
+    for (size_t c = 0; c < cands.size() && e == hipSuccess; ++c) {
+        build_plan(prog, dtype, cands[c].tj, scratch, &plans[c]);
+        e = enqueue(plans[c], cands[c], st, true);
+    }
+    for (int r = 0; r < ROUNDS && e == hipSuccess; ++r)
+        for (size_t c = 0; c < cands.size() && e == hipSuccess; ++c) {
+            e = hipEventRecord(e0, st);
+            if (e == hipSuccess) e = enqueue(plans[c], cands[c], st, true);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            ms[c].push_back(t);
         }
-        if (ms < best_ms) {
-            best_ms = ms;
-            *best = v;
+    int rc = STENCIL_OK;
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "autotune");
+    } else {
+        float best_ms = 1e30f;
+        for (size_t c = 0; c < cands.size(); ++c) {
+            std::vector<float> v = ms[c];
+            std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
+            if (v[v.size() / 2] < best_ms) {
+                best_ms = v[v.size() / 2];
+                *best = cands[c];
+            }
         }
     }
     hipEventDestroy(e0);
