@@ -267,7 +267,11 @@ def variant_adjoint(n=256, nk=80):
             B.stencil_hdiff_vadv_adjoint(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT,
                                          g["w"], *gs)
         w, k = time_calls(fn, [None], 20, 3)
-        out[dtype] = {"ms": w, "Gpoints_s": n * n * nk / (w * 1e-3) / 1e9}
+        # u with its ring, coeff, wcon, a, b, c, w in; gu (interior and ring),
+        # gcoeff, gwcon out
+        ab = ES[dtype] * (2 * u_cells(n, n, nk) + 8 * n * n * nk)
+        out[dtype] = {"ms": w, "Gpoints_s": n * n * nk / (w * 1e-3) / 1e9,
+                      "algorithmic_GBs": ab / (k * 1e-3) / 1e9}
     return out
 
 
