@@ -354,13 +354,14 @@ def cpu_baseline(ni, nj, nk, budget_s=10.0):
                       % (reps, ni, nj, nk, el)}
 
 
-# Profiling commands (run from the repository root $R on the MI355X machine) whose
+# Profiling commands (run from the repository root $R on the MI355X machine,
+# writing under the directory $OUT) whose
 # output --summarize-profiles turns into the committed summaries.
 TRACE_CMD = ("cd /tmp && TMPDIR=/tmp rocprofv3 --kernel-trace --stats --output-format csv "
-             "-d $R/gpurun_out/prof_trace -o trace -- python $R/bench.py --quick --with-copy "
+             "-d $OUT/prof_trace -o trace -- python $R/bench.py --quick --with-copy "
              "--steps 20 --warmup 2")
 PMC_CMD = ("cd /tmp && TMPDIR=/tmp timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv "
-           "-d $R/gpurun_out/prof_{t} -o {t} -- python $R/bench.py --quick --with-copy "
+           "-d $OUT/prof_{t} -o {t} -- python $R/bench.py --quick --with-copy "
            "--steps 4 --warmup 1")
 COPY_PROBE_BYTES = 1 << 30
 
@@ -386,7 +387,7 @@ def summarize_profiles(outdir):
     avg_us = float(col["AverageNs"]) / 1e3
     ab = fused_bytes(512, 512, 80, 4)
     out = ["# Kernel trace: fused hdiff+vadv, FP32 512x512x80 (%s)" % kname.split("<")[0].split()[-1],
-           "", "Command (from the repository root `$R` on the MI355X machine):", "", "```", TRACE_CMD, "```", "",
+           "", "Command (from the repository root `$R` on the MI355X machine, output under `$OUT`):", "", "```", TRACE_CMD, "```", "",
            "| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
     for r in rows:
         out.append("| `%s` | %s | %.2f | %.2f | %.2f | %.1f%% |" % (
@@ -431,7 +432,7 @@ def summarize_profiles(outdir):
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(t, fh, indent=1)
     md = ["# HBM traffic of the fused kernel (FP32, 512x512x80, halo 2)", "",
-          "Two counter runs (one counter each), from the repository root `$R` on the MI355X machine:", "",
+          "Two counter runs (one counter each), from the repository root `$R` on the MI355X machine, output under `$OUT`:", "",
           "```"] + t["commands"] + ["```", "",
           "`--with-copy` also runs the 1 GiB copy probe (`k_copy16`), which calibrates the counters:", "",
           "| kernel | FETCH_SIZE (KiB/dispatch) | WRITE_SIZE (KiB/dispatch) |", "|---|---|---|",
@@ -449,9 +450,9 @@ def summarize_profiles(outdir):
 
 
 VARIANT_TRACE_CMD = ("cd /tmp && TMPDIR=/tmp rocprofv3 --kernel-trace --stats --output-format csv "
-                     "-d $R/gpurun_out/v_{v}_trace -o t -- python $R/bench.py --only {v}")
+                     "-d $OUT/v_{v}_trace -o t -- python $R/bench.py --only {v}")
 VARIANT_PMC_CMD = ("cd /tmp && TMPDIR=/tmp timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv "
-                   "-d $R/gpurun_out/v_{v}_{t} -o t -- python $R/bench.py --only {v}")
+                   "-d $OUT/v_{v}_{t} -o t -- python $R/bench.py --only {v}")
 
 
 def summarize_variant(outdir, name, fetch_calibration):
@@ -477,7 +478,7 @@ def summarize_variant(outdir, name, fetch_calibration):
     rows = list(csv.DictReader(open(one("v_%s_trace/**/*kernel_stats.csv" % name))))
     fe, wr = per_kernel("fetch", "FETCH_SIZE"), per_kernel("write", "WRITE_SIZE")
     md = ["# Kernel trace: `bench.py --only %s`" % name, "",
-          "Commands (from the repository root `$R` on the MI355X machine):", "", "```",
+          "Commands (from the repository root `$R` on the MI355X machine, output under `$OUT`):", "", "```",
           VARIANT_TRACE_CMD.format(v=name)]
     if fe:
         md += [VARIANT_PMC_CMD.format(c="FETCH_SIZE", v=name, t="fetch"),
