@@ -104,3 +104,23 @@ def test_halo_and_layout_checks():
             k({"u": other, "coeff": coeff}, {"out": u.like(fill=0.0)})
     finally:
         k.close()
+
+
+@pytest.mark.parametrize("tiled", [False, True])
+def test_two_outputs(tiled):
+    # A program may return several applies: here the Laplacian and the update.
+    p = F.hdiff_program()
+    lap = next(a for a in p.applies if a.name == "lap")
+    p.output(lap)
+    assert [o.name for o in p.outputs] == ["out", "lap"]
+    ni, nj, nk = 70, 11, 4
+    f = inputs.fields(ni, nj, nk, 2, seed=SEED + 74, storage="f64", vadv=False)
+    u = B.Field.from_numpy(f["u"], 2, "f64")
+    coeff = B.Field.from_numpy(f["coeff"], 2, "f64")
+    out, lp = u.like(fill=-7.0), u.like(fill=-7.0)
+    with F.compile_program(p, "f64", like=u, unroll=2, tiled=tiled) as k:
+        k({"u": u, "coeff": coeff}, {"out": out, "lap": lp})
+        torch.cuda.synchronize()
+    assert normwise(out.to_numpy(interior=True), oracle.hdiff(f["u"], 2, f["coeff"], 2)) <= TOL["f64"]
+    assert normwise(lp.to_numpy(interior=True), oracle.lap(f["u"], 2)) <= TOL["f64"]
+    assert halo_untouched(out) and halo_untouched(lp)
