@@ -115,13 +115,10 @@ def fused(cfg=None):
     return fn
 
 
-def errors(f, x):
-    import oracle
-    ref = oracle.hdiff_vadv(f["u"], 2, f["coeff"], 2, f["wcon"], 2, f["a"], 2, f["b"], 2, f["c"], 2,
-                            DT)
-    got = x.to_numpy(interior=True)
-    return {"normwise": float(np.abs(got - ref).max() / np.abs(ref).max()),
-            "rms": float(np.sqrt(np.mean((got - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))}
+def gpu_output(f, x):
+    """One GPU result kept on the host for the CPU leg to check: the inputs it
+    was computed from and its interior."""
+    return {"f": f, "x": x.to_numpy(interior=True)}
 
 
 def copy_probe():
@@ -196,9 +193,8 @@ def variant_column(ni, nj, nk, dtype, level):
     ab = fused_bytes(ni, nj, nk, es)
     out = {"Gpoints_s": ni * nj * nk / (w * 1e-3) / 1e9, "ms": w,
            "algorithmic_GBs": ab / (k * 1e-3) / 1e9,
-           "frac_hbm_peak": ab / (k * 1e-3) / 1e9 / PEAK_HBM_GBS,
-           "error_vs_fp64_oracle": errors(sets[0][0], sets[0][1]["x"])}
-    return out
+           "frac_hbm_peak": ab / (k * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    return out, gpu_output(sets[0][0], sets[0][1]["x"])
 
 
 def variant_hdiff_levels(ni, nj, nk):
@@ -337,21 +333,37 @@ def variant_jvp(n=256, nk=80):
     return out
 
 
-def cpu_baseline(ni, nj, nk, budget_s=10.0):
+def relative_errors(got, ref):
+    return {"normwise": float(np.abs(got - ref).max() / np.abs(ref).max()),
+            "rms": float(np.sqrt(np.mean((got - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))}
+
+
+def cpu_baseline(ni, nj, nk, checks, budget_s=10.0):
+    """The host leg: times the FP64 oracle on the workload, then uses it to
+    check the GPU outputs in checks (label -> gpu_output); returns the
+    baseline record and the errors per label."""
     import oracle
     from paper_2005_13014_amd import inputs
+
+    def run(f):
+        return oracle.hdiff_vadv(f["u"], 2, f["coeff"], 2, f["wcon"], 2, f["a"], 2, f["b"], 2, f["c"],
+                                 2, DT)
     f = inputs.fields(ni, nj, nk, 2, seed=SEED + 3, storage="f32")
     reps, t0 = 0, time.perf_counter()
     while True:
-        oracle.hdiff_vadv(f["u"], 2, f["coeff"], 2, f["wcon"], 2, f["a"], 2, f["b"], 2, f["c"], 2, DT)
+        run(f)
         reps += 1
         el = time.perf_counter() - t0
         if el >= budget_s or reps >= 20:
             break
-    return {"value": reps * ni * nj * nk / el / 1e9, "unit": "Gpoints/s", "cores": 1,
+    base = {"value": reps * ni * nj * nk / el / 1e9, "unit": "Gpoints/s", "cores": 1,
             "kind": "oracle",
             "sample": "%d full calls of the FP64 oracle on the %dx%dx%d workload (%.1f s, one thread)"
                       % (reps, ni, nj, nk, el)}
+    errs = {}
+    for label, c in checks.items():
+        errs[label] = relative_errors(c["x"], run(c["f"]))
+    return base, errs
 
 
 # Profiling commands (run from the repository root $R on the MI355X machine,
@@ -612,10 +624,9 @@ def main():
         print(json.dumps(result), flush=True)
         return
 
-    log("checking errors against the oracle")
     fused(cfg)(sets[0][1])
     torch.cuda.synchronize()
-    result["error_vs_fp64_oracle"] = errors(sets[0][0], sets[0][1]["x"])
+    checks = {"headline": gpu_output(sets[0][0], sets[0][1]["x"])}
     del sets
     torch.cuda.empty_cache()
     variants = {"copy_probe_GBs": copy_probe(), "read_probe_GBs": read_probe(),
@@ -624,11 +635,12 @@ def main():
     for label, dt_, level in (("fused_f64", "f64", 0), ("original_f64", "f64", 1),
                               ("fused_bf16", "bf16", 0)):
         log("variant", label)
-        variants[label] = variant_column(ni, nj, nk, dt_, level)
+        variants[label], checks[label] = variant_column(ni, nj, nk, dt_, level)
         torch.cuda.empty_cache()
     for dt_ in ("f32", "f64"):  # the configuration's other size
         log("variant fused_%s_256x256x80" % dt_)
-        variants["fused_%s_256x256x80" % dt_] = variant_column(256, 256, 80, dt_, 0)
+        label = "fused_%s_256x256x80" % dt_
+        variants[label], checks[label] = variant_column(256, 256, 80, dt_, 0)
         torch.cuda.empty_cache()
     variants["speedup_fused_f32_over_original_f64"] = variants["original_f64"]["ms"] / wall
     log("variant hdiff optimisation levels")
@@ -649,8 +661,11 @@ def main():
     log("variant front end: generated hdiff 512x512x80")
     variants["frontend_hdiff_f32_512x512x80"] = variant_frontend()
     result["variants"] = variants
-    log("cpu baseline (oracle)")
-    result["cpu_baseline"] = cpu_baseline(ni, nj, nk)
+    log("cpu baseline (oracle): timing, then checking the GPU outputs against it")
+    result["cpu_baseline"], errs = cpu_baseline(ni, nj, nk, checks)
+    result["error_vs_fp64_oracle"] = errs.pop("headline")
+    for label, e in errs.items():
+        variants[label]["error_vs_fp64_oracle"] = e
     print(json.dumps(result), flush=True)
 
 
