@@ -41,17 +41,21 @@ STENCIL_API int stencil_rtc_compile(const char *source, const char *kernel_name,
     const hiprtcResult rc = hiprtcCompileProgram(prog, static_cast<int>(sizeof(opts) / sizeof(opts[0])), opts);
     if (rc != HIPRTC_SUCCESS) {
         size_t n = 0;
-        hiprtcGetProgramLogSize(prog, &n);
+        if (hiprtcGetProgramLogSize(prog, &n) != HIPRTC_SUCCESS) n = 0;
         std::string log(n + 1, '\0');
-        hiprtcGetProgramLog(prog, &log[0]);
+        if (n && hiprtcGetProgramLog(prog, &log[0]) != HIPRTC_SUCCESS) log = "(no log)";
         hiprtcDestroyProgram(&prog);
         return fail(STENCIL_E_ARG, "rtc_compile: %s", log.c_str());
     }
     size_t size = 0;
-    hiprtcGetCodeSize(prog, &size);
-    std::vector<char> code(size);
-    hiprtcGetCode(prog, code.data());
+    std::vector<char> code;
+    bool got = hiprtcGetCodeSize(prog, &size) == HIPRTC_SUCCESS && size > 0;
+    if (got) {
+        code.resize(size);
+        got = hiprtcGetCode(prog, code.data()) == HIPRTC_SUCCESS;
+    }
     hiprtcDestroyProgram(&prog);
+    if (!got) return fail(STENCIL_E_HIP, "rtc_compile: no code object from hipRTC");
 
     RtcKernel *k = new RtcKernel;
     hipError_t e = hipModuleLoadData(&k->module, code.data());
