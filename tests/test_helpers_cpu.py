@@ -40,3 +40,23 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_bench_cpu_leg_times_the_oracle_and_checks_kept_outputs():
+    """The benchmark's host leg: the oracle timed on a bounded sample, then
+    each GPU output it was handed compared with the oracle's result on the
+    same inputs (here stand-ins: the exact result and a perturbed copy)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    ni, nj, nk = 20, 9, 6
+    f = inputs.fields(ni, nj, nk, 2, seed=bench.SEED + 3, storage="f32")
+    ref = oracle.hdiff_vadv(f["u"], 2, f["coeff"], 2, f["wcon"], 2, f["a"], 2, f["b"], 2, f["c"], 2,
+                            bench.DT)
+    bad = ref.copy()
+    bad[1, 2, 3] += 1e-3 * np.abs(ref).max()
+    base, errs = bench.cpu_baseline(ni, nj, nk, {"exact": {"f": f, "x": ref}, "bad": {"f": f, "x": bad}},
+                                    budget_s=0.05)
+    assert base["kind"] == "oracle" and base["unit"] == "Gpoints/s" and base["cores"] == 1
+    assert base["value"] > 0 and "%dx%dx%d" % (ni, nj, nk) in base["sample"]
+    assert errs["exact"] == {"normwise": 0.0, "rms": 0.0}
+    assert abs(errs["bad"]["normwise"] - 1e-3) < 1e-9 and errs["bad"]["rms"] > 0
