@@ -63,6 +63,23 @@ def test_generated_hdiff_low_precision_under_its_own_masks(unroll, tiled, dtype)
     assert halo_untouched(out)
 
 
+@pytest.mark.parametrize("tiled", [False, True])
+def test_generated_hdiff_f32_at_the_benchmarked_size(tiled):
+    """512 x 512 x 80 FP32, every unroll factor the benchmark times: every
+    element against the FP64 oracle under the FP32 limiter decisions."""
+    ni, nj, nk = 512, 512, 80
+    note("front end hdiff f32 512x512x80 tiled=%s" % tiled)
+    f = inputs.fields(ni, nj, nk, 2, seed=SEED + 1, storage="f32", vadv=False)
+    kx, ky = limiter_masks(f["u"], 2, "f32")
+    ref = oracle.hdiff(f["u"], 2, f["coeff"], 2, force_kx=kx, force_ky=ky)
+    for unroll in (1, 2, 4):
+        out = run_hdiff(f, "f32", unroll, tiled)
+        err = normwise(out.to_numpy(interior=True), ref)
+        note("unroll %d normwise %.2e" % (unroll, err))
+        assert err <= TOL["f32"]
+        assert halo_untouched(out)
+
+
 def test_generated_biharmonic():
     # A program the hand-written kernels do not cover: out = u - c lap(lap(u)).
     p = F.Program()
