@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import DT, SEED, TOL, gpu_fields, halo_untouched, interior, normwise, out_field, rms_rel
+from helpers import (DT, SEED, TOL, gpu_fields, halo_untouched, interior, limiter_masks, normwise, out_field,
+                     rms_rel)
 from paper_2005_13014_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -56,6 +57,27 @@ def test_hdiff(dtype, shape, variant):
     ref = oracle.hdiff(f["u"], 2, f["coeff"], 2)
     got = out.to_numpy(interior=True)
     assert normwise(got, ref) <= TOL[dtype], normwise(got, ref)
+    assert halo_untouched(out)
+
+
+@pytest.mark.parametrize("variant", ["u1", "u2", "u4", "original"])
+def test_hdiff_f32_at_the_benchmarked_size(variant):
+    """hdiff alone, FP32, 512 x 512 x 80 at every optimisation level the
+    benchmark times: every element against the FP64 oracle taking the FP32
+    limiter decisions."""
+    ni, nj, nk = 512, 512, 80
+    note("hdiff f32 512x512x80", variant)
+    f = inputs.fields(ni, nj, nk, 2, seed=SEED + 1, storage="f32", vadv=False)
+    g = gpu_fields(f, 2, "f32", ("u", "coeff"))
+    out = out_field(ni, nj, nk, 2, "f32")
+    cfg = B.config(level=1) if variant == "original" else B.config(unroll=int(variant[1]))
+    B.stencil_hdiff(g["u"], g["coeff"], out, cfg=cfg)
+    torch.cuda.synchronize()
+    kx, ky = limiter_masks(f["u"], 2, "f32")
+    ref = oracle.hdiff(f["u"], 2, f["coeff"], 2, force_kx=kx, force_ky=ky)
+    err = normwise(out.to_numpy(interior=True), ref)
+    note("normwise %.2e" % err)
+    assert err <= TOL["f32"]
     assert halo_untouched(out)
 
 
@@ -110,6 +132,22 @@ def test_hdiff_vadv(dtype, shape, level):
     ref = ref_hdiff_vadv(f, 2)
     got = x.to_numpy(interior=True)
     assert normwise(got, ref) <= TOL[dtype], normwise(got, ref)
+    assert halo_untouched(x)
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_fp64_at_the_benchmarked_size(level):
+    """FP64 hdiff + vadv on 512 x 512 x 80, fused (level 0) and the unfused
+    original path (level 1), as the benchmark times them: every element
+    within 1e-12 of the oracle."""
+    ni, nj, nk = 512, 512, 80
+    note("hdiff_vadv f64 512x512x80 level", level)
+    f = inputs.fields(ni, nj, nk, 2, seed=SEED + 3, storage="f64")
+    x = run_hdiff_vadv(f, ni, nj, nk, 2, "f64", cfg=B.config(level=level))
+    ref = ref_hdiff_vadv(f, 2)
+    got = x.to_numpy(interior=True)
+    note("normwise %.3e rms %.3e" % (normwise(got, ref), rms_rel(got, ref)))
+    assert normwise(got, ref) <= 1e-12 and rms_rel(got, ref) <= 1e-12
     assert halo_untouched(x)
 
 
