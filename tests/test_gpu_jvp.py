@@ -104,13 +104,14 @@ def test_jvp_tangent_subsets(subset):
         check(dx, ref, TOL["f64"], "jvp subset %s" % (subset,))
 
 
-def test_jvp_headline_size_f32():
-    # The size the benchmark times the reverse mode at, FP32 storage.
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_jvp_headline_size(dtype):
+    # The size the benchmark times forward mode at, FP32 and FP64 storage.
     ni, nj, nk = 256, 256, 80
-    note("jvp f32 256x256x80")
-    f, v, g, gv = setup(ni, nj, nk, "f32", SEED + 63)
-    ref = oracle_jvp(f, v, limiter_masks(f["u"], 2, "f32"))
-    check(gpu_jvp(g, gv), ref, TOL["f32"], "jvp f32 256x256x80")
+    note("jvp %s 256x256x80" % dtype)
+    f, v, g, gv = setup(ni, nj, nk, dtype, SEED + 63)
+    ref = oracle_jvp(f, v, limiter_masks(f["u"], 2, dtype))
+    check(gpu_jvp(g, gv), ref, TOL[dtype], "jvp %s 256x256x80" % dtype)
 
 
 def test_jvp_duality_with_gpu_adjoint():

@@ -135,13 +135,13 @@ def test_hdiff_vadv(dtype, shape, level):
     assert halo_untouched(x)
 
 
-@pytest.mark.parametrize("level", [0, 1])
-def test_fp64_at_the_benchmarked_size(level):
-    """FP64 hdiff + vadv on 512 x 512 x 80, fused (level 0) and the unfused
+@pytest.mark.parametrize("n,level", [(512, 0), (512, 1), (256, 0)])
+def test_fp64_at_the_benchmarked_size(n, level):
+    """FP64 hdiff + vadv on n x n x 80, fused (level 0) and the unfused
     original path (level 1), as the benchmark times them: every element
     within 1e-12 of the oracle."""
-    ni, nj, nk = 512, 512, 80
-    note("hdiff_vadv f64 512x512x80 level", level)
+    ni, nj, nk = n, n, 80
+    note("hdiff_vadv f64 %dx%dx80 level %d" % (n, n, level))
     f = inputs.fields(ni, nj, nk, 2, seed=SEED + 3, storage="f64")
     x = run_hdiff_vadv(f, ni, nj, nk, 2, "f64", cfg=B.config(level=level))
     ref = ref_hdiff_vadv(f, 2)
