@@ -181,9 +181,9 @@ static hipError_t launch_hdiff_t(HdiffArgs a, hipStream_t st) {
 template <class T>
 static hipError_t hdiff_unroll(const HdiffArgs &a, int unroll, hipStream_t st) {
     switch (unroll) {
-    case 1: return launch_hdiff_t<T, 4, 1, 4>(a, st);
-    case 2: return launch_hdiff_t<T, 4, 2, 4>(a, st);
-    case 4: return launch_hdiff_t<T, 4, 4, 4>(a, st);
+    case 1: return launch_hdiff_t<T, 16, 1, 4>(a, st);
+    case 2: return launch_hdiff_t<T, 8, 2, 4>(a, st);
+    case 4: return launch_hdiff_t<T, 8, 4, 4>(a, st);
     }
     return hipErrorInvalidValue;
 }
