@@ -60,3 +60,30 @@ def test_bench_cpu_leg_times_the_oracle_and_checks_kept_outputs():
     assert base["value"] > 0 and "%dx%dx%d" % (ni, nj, nk) in base["sample"]
     assert errs["exact"] == {"normwise": 0.0, "rms": 0.0}
     assert abs(errs["bad"]["normwise"] - 1e-3) < 1e-9 and errs["bad"]["rms"] > 0
+
+
+def test_product_path_and_oracle_are_independent():
+    """The package and the library sources never import, include or link
+    the oracle, and the oracle never uses the package's kernels or headers:
+    the two share only the seeded input generators."""
+    import ast
+    import glob
+    pkg = os.path.join(ROOT, "paper_2005_13014_amd")
+    for path in glob.glob(os.path.join(pkg, "*.py")):
+        tree = ast.parse(open(path).read())
+        for node in ast.walk(tree):
+            names = []
+            if isinstance(node, ast.Import):
+                names = [a.name for a in node.names]
+            elif isinstance(node, ast.ImportFrom):
+                names = [node.module or ""]
+            assert not any(n == "oracle" or n.startswith("oracle.") for n in names), path
+    for path in glob.glob(os.path.join(pkg, "csrc", "*")) + glob.glob(os.path.join(ROOT, "include", "*")):
+        text = open(path).read()
+        assert "oracle" not in text, path
+    for path in glob.glob(os.path.join(ROOT, "oracle", "*")):
+        if os.path.isdir(path) or path.endswith((".so", ".o", ".pyc")):
+            continue
+        text = open(path, errors="replace").read()
+        assert "paper_2005_13014_amd.binding" not in text and "libstencil" not in text, path
+        assert "csrc" not in text and "stencil.h" not in text, path
