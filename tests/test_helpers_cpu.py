@@ -87,3 +87,22 @@ def test_product_path_and_oracle_are_independent():
         text = open(path, errors="replace").read()
         assert "paper_2005_13014_amd.binding" not in text and "libstencil" not in text, path
         assert "csrc" not in text and "stencil.h" not in text, path
+
+
+def test_missing_library_fails_loudly():
+    """Without the built library every entry point raises; there is no
+    fallback path (run in a child process so this one's loaded library is
+    untouched)."""
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2005_13014_amd import binding as B\n"
+        "B.LIB_PATH = '/nonexistent/libstencil.so'\n"
+        "try:\n"
+        "    B.lib()\n"
+        "except RuntimeError as e:\n"
+        "    print('raised:', e)\n"
+        "    sys.exit(0)\n"
+        "sys.exit(3)\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "not built" in r.stdout
