@@ -34,6 +34,7 @@ __device__ __forceinline__ C limit(C f, C du) {
 // TO = T writes the storage dtype; TO = C keeps the compute type (scratch).
 // Fields are addressed through raw buffers (column.hpp): u from its cell
 // (-2, -2, 0), coeff and out from their origins; the level offset is scalar.
+// (With TO = T = C, as for FP64 and FP32 storage, the buffer store is taken.)
 template <class T, class TO, int TJ, int UJ, int PF>
 __global__ __launch_bounds__(64 * TJ) void k_hdiff(HdiffArgs p) {
     using S = Storage<T>;
@@ -58,6 +59,7 @@ __global__ __launch_bounds__(64 * TJ) void k_hdiff(HdiffArgs p) {
     const auto ru = make_rsrc(static_cast<const char *>(p.u) - (2 + 2 * sj) * static_cast<int>(ES),
                               p.u_bytes);
     const auto rcf = make_rsrc(p.coeff, p.col_bytes);
+    const auto rout = make_rsrc(p.out, p.col_bytes);
 
     // Tile element (r, c) holds u(i0 - 2 + c, j0 - 2 + r); loads past the
     // addressable ring are clamped onto valid cells (never read by an active lane).
@@ -144,11 +146,15 @@ __global__ __launch_bounds__(64 * TJ) void k_hdiff(HdiffArgs p) {
                     const C fw = limit(lc[v + 1] - lw, uc[v + 1] - cv[-1]);
                     const C h = uc[v + 1] - cf[v] * (fe - fw + fy[v + 1] - fy[v]);
                     if (cact[v]) {
-                        const uint32_t o = vcol[v] / ES + static_cast<uint32_t>(k) * p.sk;
-                        if constexpr (std::is_same<TO, C>::value)
+                        if constexpr (std::is_same<TO, T>::value) {
+                            // Storage output: a non-temporal buffer store (no output
+                            // line displaces the inputs' halo rows in the caches).
+                            IO::template store_d<2>(rout, vcol[v], static_cast<uint32_t>(k) * skb,
+                                                    static_cast<double>(h));
+                        } else {
+                            const uint32_t o = vcol[v] / ES + static_cast<uint32_t>(k) * p.sk;
                             static_cast<TO *>(p.out)[o] = h;
-                        else
-                            S::store(static_cast<TO *>(p.out) + o, h);
+                        }
                     }
                 }
             }
