@@ -24,12 +24,31 @@
  *    extents and the same strides (sj, sk).
  *  - Only the interior of an output is written; its halo is never touched.
  *  - Outputs must not overlap any input or other output (stencil programs are
- *    alias-free, Sec. IV-E); overlap of the addressed byte ranges is rejected.
+ *    alias-free, Sec. IV-C and IV-D); overlap of the addressed byte ranges is rejected.
  *  - Input halos must be at least the access extent that shape inference
  *    derives for the call (Sec. V-B); otherwise STENCIL_E_HALO.
  *  - Calls validate on the host, then enqueue asynchronously on the given HIP
- *    stream (a hipStream_t passed as void*; NULL = the null stream) and never
- *    synchronise.  Validation errors return before anything is enqueued.
+ *    stream (a hipStream_t passed as void*; NULL = the null stream).
+ *    Validation errors return before anything is enqueued.
+ *  - Synchronisation and allocation.  No call synchronises, allocates or frees
+ *    device memory except these, and only in the case named:
+ *      (1) calls that use library scratch -- stencil_hdiff, stencil_vadv and
+ *          stencil_hdiff_vadv when they run the unfused kernels (level
+ *          ORIGINAL, or a size the fused kernels do not take), and
+ *          stencil_hdiff_vadv_adjoint -- when they need more scratch than the
+ *          stream's buffer holds (the first such call on a stream, or a
+ *          larger one): the stream is synchronised, the old buffer freed and
+ *          a larger one allocated;
+ *      (2) stencil_program_run on the first run of a program signature: it
+ *          allocates the program's scratch (shared with cached programs of
+ *          the same size on the same stream), with STENCIL_PROGRAM_AUTOTUNE
+ *          synchronises the stream to time the candidates, and when the
+ *          cache is full evicts the least recently used program (waiting for
+ *          that program's stream, then freeing its graph and scratch);
+ *      (3) stencil_shutdown (synchronises the device, frees everything).
+ *    On a stream that is being captured into a graph such a call returns
+ *    STENCIL_E_UNSUPPORTED instead of allocating (make it once before the
+ *    capture, so the scratch exists); every other call captures normally.
  *  - Empty interiors (ni, nj or nk == 0) are valid no-ops.
  *  - Every element offset must fit in a signed 32-bit integer.
  *  - Return value: STENCIL_OK or an error code; stencil_last_error() gives a
@@ -117,9 +136,11 @@ typedef struct {
  *   out = u - coeff * (flx - flx(i-1) + fly - fly(j-1))
  * The paper names this benchmark (Sec. VII-B, Table II: four stencil
  * operators, a min-style limiter) without printing its formula; the limiter is
- * branch-free control flow inside the operator (Sec. IV-F).
+ * branch-free control flow inside the operator (Sec. IV-E).
  * Inputs: u (halo >= 2 in i and j), coeff (interior read only).
- * Output: out (interior written).  cfg: level, unroll. */
+ * Output: out (interior written).  cfg: level, unroll.  Fields whose
+ * addressed span is 2 GiB or more run the unfused kernels (library scratch);
+ * level INLINE then returns STENCIL_E_UNSUPPORTED. */
 int stencil_hdiff(const stencil_field_t *u, const stencil_field_t *coeff,
                   const stencil_field_t *out, const stencil_config_t *cfg, void *stream);
 
@@ -156,7 +177,7 @@ int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field_t *coeff,
  *   gwcon(k) = sum over faces f of k of Fhat(f) * hbar(f) / 2
  *   gcoeff = -gh * (flx - flx(i-1) + fly - fly(j-1))
  *   gu = gh + masked transposed flux and Laplacian stencils applied to gh
- * Inputs: u (halo >= 2), coeff, wcon, a, b, c, w (interior read only).
+ * and, optionally, the gradients of the tridiagonal matrix
  *   ga(k) = -lam(k) x(k-1), gb(k) = -lam(k) x(k), gc(k) = -lam(k) x(k+1)
  *                             (ga(0) = gc(K-1) = 0: those entries lie outside
  *                             the matrix)
@@ -167,8 +188,10 @@ int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field_t *coeff,
  * overwritten; the four 3-cell corner notches of the ring receive 0),
  * gcoeff and gwcon (interior); optionally ga, gb, gc (interior; NULL skips
  * each, and x may be NULL when all three are NULL).  Uses library-owned
- * device scratch.  nk <= 96 and fields below 2 GiB in the compute type
- * (FP32 for bfloat16 storage); STENCIL_E_UNSUPPORTED otherwise. */
+ * device scratch: one field-sized plane of the compute type (FP64 storage:
+ * two), see the synchronisation rules above.  nk <= 96 and fields below
+ * 2 GiB in the compute type (FP32 for bfloat16 storage);
+ * STENCIL_E_UNSUPPORTED otherwise. */
 int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stencil_field_t *coeff,
                                const stencil_field_t *wcon, const stencil_field_t *a,
                                const stencil_field_t *b, const stencil_field_t *c, double dt,
@@ -228,7 +251,7 @@ typedef struct {
 } stencil_subdomain_t;
 
 /* A timestep program over independent subdomains of different sizes
- * (a stencil program with eager program-level control, Sec. IV-F).
+ * (a stencil program with eager program-level control, Sec. IV-E).
  * stages: HDIFF|VADV, HDIFF|VADV|VDIFF or HDIFF|VADV|VDIFF|HGRAD, or either
  * of the last two with VDIFF_IMPLICIT in place of VDIFF.
  * Shape inference (Sec. V-B) derives the halos: with HGRAD the earlier stages
@@ -251,14 +274,19 @@ enum {
 
 /* Runs the program.  All fields of one subdomain share dtype, extents and
  * strides; subdomains may differ in size and layout.  Output z of each field
- * is written on its interior.  Uses library-owned device scratch. */
+ * is written on its interior.  The plan, the tuned variant, the scratch and
+ * the graph are cached on the program's full signature (device, stream,
+ * stages, flags, parameters and every descriptor, compared exactly); the
+ * cache holds the 16 most recently used programs.  Programs on the same
+ * stream whose scratch has the same size share it.  See the
+ * synchronisation rules above for the first run of a signature. */
 int stencil_program_run(const stencil_program_t *prog, void *stream);
 
 /* ---- run-time compiled stencil programs ---------------------------------- */
 
 /* The stencil-program front end (Python, paper_2005_13014_amd/frontend.py)
  * turns a program of stencil applies into one inlined, unrolled kernel whose
- * extents and strides are compile-time constants (Sec. IV-V), as HIP source.
+ * extents and strides are compile-time constants (Sec. IV-B), as HIP source.
  * stencil_rtc_compile builds it for gfx950 with hipRTC (the library's own
  * code-generation flags) and returns an opaque handle owned by the caller
  * (release with stencil_rtc_release).  source: NUL-terminated HIP source;
@@ -279,6 +307,11 @@ int stencil_rtc_release(void *handle);
 
 /* Message describing the calling thread's last nonzero return code. */
 const char *stencil_last_error(void);
+
+/* Device memory the library holds on all devices (scratch buffers and
+ * cached programs), in bytes; *programs (if not NULL) receives the number
+ * of cached programs. */
+int64_t stencil_held_memory(int32_t *programs);
 
 /* STENCIL_ABI_VERSION of the loaded library. */
 int stencil_abi_version(void);

@@ -78,6 +78,13 @@ class HdiffVadv(torch.autograd.Function):
 
 def hdiff_vadv(u, coeff, wcon, a, b, c, dt):
     """Differentiable x = vadv(hdiff(u, coeff), wcon, a, b, c, dt) on Fields;
-    returns a Field whose ``buf`` carries the autograd graph."""
+    returns a Field whose ``buf`` carries the autograd graph.  The function
+    passes buffers through autograd and describes every one of them with u's
+    layout, so all six fields must share it exactly (ValueError otherwise)."""
+    lay = u.layout()
+    for name, f in (("coeff", coeff), ("wcon", wcon), ("a", a), ("b", b), ("c", c)):
+        if f.layout() != lay:
+            raise ValueError("%s has layout %s but u has %s (origin, extents, halos, strides, dtype, "
+                             "buffer size must match)" % (name, f.layout(), lay))
     buf = HdiffVadv.apply(u.buf, coeff.buf, wcon.buf, a.buf, b.buf, c.buf, (u, float(dt)))
     return _wrap(buf, u)

@@ -85,6 +85,7 @@ _SIGNATURES = {
     "stencil_last_error": [],
     "stencil_abi_version": [],
     "stencil_shutdown": [],
+    "stencil_held_memory": [ctypes.POINTER(ctypes.c_int32)],
     "stencil_probe_copy": [_V, _V, ctypes.c_int64, _V],
     "stencil_probe_read": [_V, ctypes.c_int64, ctypes.c_uint32, _V, _V],
     "stencil_probe_streams": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, _V, ctypes.c_int64, _V],
@@ -107,6 +108,7 @@ def lib():
             fn.restype = ctypes.c_int
         handle.stencil_last_error.restype = ctypes.c_char_p
         handle.stencil_shutdown.restype = None
+        handle.stencil_held_memory.restype = ctypes.c_int64
         _lib = handle
     return _lib
 
@@ -182,8 +184,21 @@ class Field:
                          self.hi, self.hj, self.sj, self.sk)
 
     def like(self, halo=None, fill=None):
-        h = self.hi if halo is None else halo
-        return Field.empty(self.ni, self.nj, self.nk, h, self.dtype, self.buf.device, fill=fill)
+        """A new field of the same extents and dtype: with halo None, the same
+        layout exactly (buffer size, origin, halos, strides); otherwise the
+        standard layout with that halo."""
+        if halo is None:
+            buf = torch.empty_like(self.buf)
+            if fill is not None:
+                buf.fill_(fill)
+            return Field(buf, self.origin, self.ni, self.nj, self.nk, self.hi, self.hj, self.sj, self.sk,
+                         self.dtype)
+        return Field.empty(self.ni, self.nj, self.nk, halo, self.dtype, self.buf.device, fill=fill)
+
+    def layout(self):
+        """Everything a descriptor takes from this field besides its buffer."""
+        return (self.origin, self.ni, self.nj, self.nk, self.hi, self.hj, self.sj, self.sk, self.dtype,
+                self.buf.numel())
 
     @property
     def shape(self):
@@ -329,3 +344,10 @@ def stencil_abi_version():
 
 def stencil_shutdown():
     lib().stencil_shutdown()
+
+
+def stencil_held_memory():
+    """(bytes of device memory the library holds, cached programs)."""
+    n = ctypes.c_int32(0)
+    b = lib().stencil_held_memory(ctypes.byref(n))
+    return int(b), int(n.value)

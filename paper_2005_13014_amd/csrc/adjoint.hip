@@ -477,9 +477,13 @@ __global__ __launch_bounds__(256) void k_hdiff_adjoint(AdjArgs p, int nbi, int n
 
 // ---------------------------------------------------------------------------
 
+// Scratch: gh, and for FP64 storage also h (FP32 and bfloat16 storage
+// evaluate h inside the column kernel); each plane in the compute type with
+// the fields' strides, 256-byte aligned.
 size_t adjoint_scratch_bytes(int dtype, int sk, int K) {
     const size_t cs = dtype == DT_F64 ? 8 : 4;
-    return 2 * (static_cast<size_t>(sk) * K * cs + 256);
+    const size_t plane = (static_cast<size_t>(sk) * K * cs + 255) / 256 * 256;
+    return dtype == DT_F64 ? 2 * plane : plane;
 }
 
 template <class T, int KH, bool FUSEH>
@@ -498,12 +502,12 @@ template <class T>
 static hipError_t adjoint_run(AdjArgs a, void *scratch, hipStream_t st) {
     using C = typename Storage<T>::C;
     const size_t plane = (static_cast<size_t>(a.sk) * a.K * sizeof(C) + 255) / 256 * 256;
-    a.h = scratch;
-    a.gh = static_cast<char *>(scratch) + plane;
     // FP32 and bfloat16 storage evaluate h inside the column kernel (FUSEH,
-    // h held in LDS); FP64's h would take twice the LDS, so it is computed by
-    // the hdiff kernel into scratch first.
+    // h held in LDS) and need only the gh plane; FP64's h would take twice
+    // the LDS, so it is computed by the hdiff kernel into a second plane first.
     constexpr bool FUSEH = !std::is_same<T, double>::value;
+    a.gh = scratch;
+    a.h = FUSEH ? scratch : static_cast<char *>(scratch) + plane;  // (never read with FUSEH)
     hipError_t e = hipSuccess;
     if constexpr (!FUSEH) {
         HdiffArgs hd{};

@@ -2,7 +2,8 @@
 //
 // Every entry point validates its descriptors on the host before anything is
 // enqueued (the checks a stencil program's asserted ranges and shape inference
-// imply, Sec. IV-E and V-B), then launches on the caller's stream.
+// imply: alias-free parameters, Sec. IV-C and IV-D; shape inference,
+// Sec. V-B), then launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -43,9 +44,18 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(STENCIL_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+#define TRY(x)                            \
+    do {                                  \
+        int rc_ = (x);                    \
+        if (rc_ != STENCIL_OK) return rc_; \
+    } while (0)
+
 // ---------------------------------------------------------------------------
 // Library-owned device scratch, one buffer per (device, stream) so that calls
-// on different streams never share temporaries.
+// on different streams never share temporaries.  A lease keeps the lock until
+// the kernels that use the buffer are enqueued: a call on another thread that
+// grows the same buffer (synchronise, free, allocate) then waits, and its
+// synchronisation also covers the kernels enqueued under the lease.
 // ---------------------------------------------------------------------------
 namespace {
 struct Scratch {
@@ -56,13 +66,36 @@ std::mutex g_scratch_mu;
 std::map<std::pair<int, hipStream_t>, Scratch> g_scratch;
 }  // namespace
 
-int scratch_get(hipStream_t st, size_t bytes, void **out) {
+struct ScratchLease {
+    std::unique_lock<std::mutex> lock;
+    void *p = nullptr;
+};
+
+// True when `st` is being captured into a graph (then nothing may allocate,
+// free or synchronise on it).
+int stream_capturing(hipStream_t st, bool *capturing) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    *capturing = cs != hipStreamCaptureStatusNone;
+    return STENCIL_OK;
+}
+
+int scratch_get(hipStream_t st, size_t bytes, ScratchLease *lease) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    std::unique_lock<std::mutex> lock(g_scratch_mu);
     Scratch &s = g_scratch[{dev, st}];
     if (s.bytes < bytes) {
+        bool capturing = false;
+        TRY(stream_capturing(st, &capturing));
+        if (capturing)
+            return fail(STENCIL_E_UNSUPPORTED,
+                        "the call needs %zu bytes of library scratch on this stream, which holds %zu; growing it "
+                        "would synchronise and allocate inside a stream capture (make the same call once before "
+                        "capturing, or use the entry point that allocates nothing)",
+                        bytes, s.bytes);
         if (s.p) {
             // Kernels enqueued earlier on this stream may still use the old buffer.
             e = hipStreamSynchronize(st);
@@ -75,8 +108,16 @@ int scratch_get(hipStream_t st, size_t bytes, void **out) {
         if (e != hipSuccess) return hip_fail(e, "hipMalloc(scratch)");
         s.bytes = bytes;
     }
-    *out = s.p;
+    lease->p = s.p;
+    lease->lock = std::move(lock);
     return STENCIL_OK;
+}
+
+long long scratch_held_bytes() {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    long long n = 0;
+    for (auto &kv : g_scratch) n += static_cast<long long>(kv.second.bytes);
+    return n;
 }
 
 void scratch_release_all() {
@@ -171,12 +212,6 @@ int check_alias(const stencil_field_t *const *fs, const char *const *names, int 
     return STENCIL_OK;
 }
 
-#define TRY(x)                            \
-    do {                                  \
-        int rc_ = (x);                    \
-        if (rc_ != STENCIL_OK) return rc_; \
-    } while (0)
-
 int check_call(const stencil_field_t *const *fs, const char *const *names, int n, int nout) {
     for (int q = 0; q < n; ++q) TRY(check_field(fs[q], names[q]));
     TRY(check_same(fs, names, n));
@@ -207,9 +242,9 @@ static int check_plain_dims(int I, int J, int K) {
 
 static int run_plain(int dtype, PlainArgs a, hipStream_t st) {
     TRY(check_plain_dims(a.I, a.J, a.K));
-    void *scratch = nullptr;
-    TRY(scratch_get(st, plain_scratch_bytes(dtype, a.I, a.J, a.K, a.vadv), &scratch));
-    a.scratch = scratch;
+    ScratchLease lease;
+    TRY(scratch_get(st, plain_scratch_bytes(dtype, a.I, a.J, a.K, a.vadv), &lease));
+    a.scratch = lease.p;
     return launch_status(launch_plain(dtype, a, st), "unfused kernels");
 }
 
@@ -349,6 +384,13 @@ STENCIL_API void stencil_shutdown(void) {
     scratch_release_all();
 }
 
+STENCIL_API int64_t stencil_held_memory(int32_t *programs) {
+    int n = 0;
+    const long long bytes = program_held_bytes(&n) + scratch_held_bytes();
+    if (programs) *programs = n;
+    return bytes;
+}
+
 STENCIL_API int stencil_hdiff(const stencil_field_t *u, const stencil_field_t *coeff,
                               const stencil_field_t *out, const stencil_config_t *cfg,
                               void *stream) {
@@ -364,7 +406,13 @@ STENCIL_API int stencil_hdiff(const stencil_field_t *u, const stencil_field_t *c
         return fail(STENCIL_E_ARG, "unroll must be 1, 2 or 4 (got %d)", c.unroll);
     if (empty(u)) return STENCIL_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (c.level == STENCIL_LEVEL_ORIGINAL) {
+    // The inlined kernel addresses u, coeff and out through raw buffers of
+    // < 2^31 bytes; larger fields take the unfused kernels (element offsets,
+    // checked above, stay 32-bit there), unless the inlined level is asked for.
+    const bool fits = column_fits(u);
+    if (!fits && c.level == STENCIL_LEVEL_INLINE)
+        return fail(STENCIL_E_UNSUPPORTED, "the inlined hdiff kernel supports fields below 2 GiB");
+    if (c.level == STENCIL_LEVEL_ORIGINAL || !fits) {
         PlainArgs a{};
         a.u = u->origin;
         a.coeff = coeff->origin;
@@ -452,15 +500,18 @@ STENCIL_API int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field
     return launch_status(launch_column(dtype, true, v, var, st), "fused hdiff+vadv kernel");
 }
 
-STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stencil_field_t *coeff,
-                                           const stencil_field_t *wcon, const stencil_field_t *a,
-                                           const stencil_field_t *b, const stencil_field_t *c,
-                                           double dt, const stencil_field_t *w,
-                                           const stencil_field_t *gu, const stencil_field_t *gcoeff,
-                                           const stencil_field_t *gwcon, const stencil_field_t *xf,
-                                           const stencil_field_t *ga, const stencil_field_t *gb,
-                                           const stencil_field_t *gc, const stencil_config_t *cfg,
-                                           void *stream) {
+namespace stl {
+
+// The reverse pass behind stencil_hdiff_vadv_adjoint and its variant that
+// allocates nothing: fixed == nullptr takes the (device, stream) scratch
+// buffer (which may grow), otherwise `fixed` (fixed_bytes long) is used and
+// a call that needs more is refused.
+int adjoint_entry(const stencil_field_t *u, const stencil_field_t *coeff, const stencil_field_t *wcon,
+                  const stencil_field_t *a, const stencil_field_t *b, const stencil_field_t *c, double dt,
+                  const stencil_field_t *w, const stencil_field_t *gu, const stencil_field_t *gcoeff,
+                  const stencil_field_t *gwcon, const stencil_field_t *xf, const stencil_field_t *ga,
+                  const stencil_field_t *gb, const stencil_field_t *gc, void *stream, void *fixed,
+                  size_t fixed_bytes) {
     // Inputs first, outputs last (the alias check takes the last nout as outputs).
     const stencil_field_t *fs[15];
     const char *names[15];
@@ -481,11 +532,9 @@ STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stenc
     TRY(check_halo(u, "u", 2));
     TRY(check_halo(gu, "gu", 2));
     TRY(check_dt(dt));
-    (void)cfg;
     if (empty(u)) return STENCIL_OK;
     if (u->nk > KMAX_ADJOINT)
         return fail(STENCIL_E_UNSUPPORTED, "adjoint supports nk <= %d", KMAX_ADJOINT);
-    if (u->nk > 65535) return fail(STENCIL_E_UNSUPPORTED, "nk too large");
     {
         // 32-bit buffer offsets, also into the compute-type scratch (FP32 for bfloat16 storage)
         const long long cells = static_cast<long long>(u->ni + 3) + static_cast<long long>(u->nj + 3) * u->sj +
@@ -505,9 +554,32 @@ STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stenc
     x.I = u->ni; x.J = u->nj; x.K = u->nk;
     x.sj = static_cast<int>(u->sj); x.sk = static_cast<int>(u->sk);
     x.dt = dt;
-    void *scratch = nullptr;
-    TRY(scratch_get(st, adjoint_scratch_bytes(u->dtype, x.sk, x.K), &scratch));
-    return launch_status(launch_adjoint(u->dtype, x, scratch, st), "adjoint kernels");
+    const size_t need = adjoint_scratch_bytes(u->dtype, x.sk, x.K);
+    if (fixed) {
+        if (need > fixed_bytes)
+            return fail(STENCIL_E_UNSUPPORTED,
+                        "the call needs %zu bytes of scratch; the fixed scratch array holds %zu", need,
+                        fixed_bytes);
+        return launch_status(launch_adjoint(u->dtype, x, fixed, st), "adjoint kernels");
+    }
+    ScratchLease lease;
+    TRY(scratch_get(st, need, &lease));
+    return launch_status(launch_adjoint(u->dtype, x, lease.p, st), "adjoint kernels");
+}
+
+}  // namespace stl
+
+STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stencil_field_t *coeff,
+                                           const stencil_field_t *wcon, const stencil_field_t *a,
+                                           const stencil_field_t *b, const stencil_field_t *c,
+                                           double dt, const stencil_field_t *w,
+                                           const stencil_field_t *gu, const stencil_field_t *gcoeff,
+                                           const stencil_field_t *gwcon, const stencil_field_t *xf,
+                                           const stencil_field_t *ga, const stencil_field_t *gb,
+                                           const stencil_field_t *gc, const stencil_config_t *cfg,
+                                           void *stream) {
+    (void)cfg;
+    return adjoint_entry(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon, xf, ga, gb, gc, stream, nullptr, 0);
 }
 
 STENCIL_API int stencil_hdiff_vadv_jvp(const stencil_field_t *u, const stencil_field_t *coeff,

@@ -20,7 +20,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
-#include <map>
+#include <list>
 #include <memory>
 #include <mutex>
 #include <vector>
@@ -98,16 +98,34 @@ struct Plan {
     size_t scratch_bytes = 0;
 };
 
+// A device buffer of y scratch, shared by the cached programs on the same
+// device and stream that need the same number of bytes: their launches are
+// ordered by that stream, so they never use it at the same time.
+struct Buffer {
+    int dev = 0;
+    hipStream_t st = nullptr;
+    size_t bytes = 0;
+    void *p = nullptr;
+    int refs = 0;
+};
+
 struct Entry {
+    std::vector<unsigned char> key;  // the full signature, compared byte for byte
+    uint64_t hash = 0;
+    int dev = 0;
+    hipStream_t st = nullptr;
     Plan plan;
-    void *scratch = nullptr;
+    Buffer *buf = nullptr;
     Variant var{0, 0};
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
 };
 
+// Cached programs, most recently used first, at most PROGRAM_CACHE_MAX.
+constexpr size_t PROGRAM_CACHE_MAX = 16;
 std::mutex g_mu;
-std::map<uint64_t, std::unique_ptr<Entry>> g_cache;
+std::list<std::unique_ptr<Entry>> g_lru;
+std::vector<std::unique_ptr<Buffer>> g_bufs;
 
 uint64_t fnv(uint64_t h, const void *p, size_t n) {
     const unsigned char *c = static_cast<const unsigned char *>(p);
@@ -118,23 +136,76 @@ uint64_t fnv(uint64_t h, const void *p, size_t n) {
     return h;
 }
 
-uint64_t signature(const stencil_program_t *prog, hipStream_t st) {
-    uint64_t h = 1469598103934665603ULL;
-    h = fnv(h, &prog->nsub, sizeof(prog->nsub));
-    h = fnv(h, &prog->stages, sizeof(prog->stages));
-    h = fnv(h, &prog->flags, sizeof(prog->flags));  // the flags choose the kernel variant
-    h = fnv(h, &prog->dt, sizeof(double) * 4);
-    h = fnv(h, &st, sizeof(st));
+// Everything a cached plan or graph depends on: device, stream, stages,
+// flags (they choose the kernel variant), parameters and every descriptor.
+std::vector<unsigned char> signature(const stencil_program_t *prog, int dev, hipStream_t st) {
+    std::vector<unsigned char> k;
+    auto put = [&](const void *p, size_t n) {
+        const unsigned char *c = static_cast<const unsigned char *>(p);
+        k.insert(k.end(), c, c + n);
+    };
+    put(&dev, sizeof(dev));
+    put(&st, sizeof(st));
+    put(&prog->nsub, sizeof(prog->nsub));
+    put(&prog->stages, sizeof(prog->stages));
+    put(&prog->flags, sizeof(prog->flags));
+    put(&prog->dt, sizeof(double));
+    put(&prog->kappa, sizeof(double));
+    put(&prog->beta_h, sizeof(double));
+    put(&prog->beta_v, sizeof(double));
     for (int s = 0; s < prog->nsub; ++s) {
         const stencil_subdomain_t &sd = prog->sub[s];
-        h = fnv(h, &sd.coeff, sizeof(stencil_field_t) * 5);
-        h = fnv(h, &sd.nfields, sizeof(sd.nfields));
-        if (sd.nfields > 0) {
-            h = fnv(h, sd.u, sizeof(stencil_field_t) * sd.nfields);
-            h = fnv(h, sd.z, sizeof(stencil_field_t) * sd.nfields);
-        }
+        for (const stencil_field_t *f : {&sd.coeff, &sd.wcon, &sd.a, &sd.b, &sd.c}) put(f, sizeof(*f));
+        put(&sd.nfields, sizeof(sd.nfields));
+        for (int q = 0; q < sd.nfields; ++q) put(&sd.u[q], sizeof(stencil_field_t));
+        for (int q = 0; q < sd.nfields; ++q) put(&sd.z[q], sizeof(stencil_field_t));
     }
-    return h;
+    return k;
+}
+
+int buffer_get(int dev, hipStream_t st, size_t bytes, Buffer **out) {
+    *out = nullptr;
+    if (!bytes) return STENCIL_OK;
+    for (auto &b : g_bufs)
+        if (b->dev == dev && b->st == st && b->bytes == bytes) {
+            ++b->refs;
+            *out = b.get();
+            return STENCIL_OK;
+        }
+    std::unique_ptr<Buffer> b(new Buffer);
+    b->dev = dev;
+    b->st = st;
+    b->bytes = bytes;
+    const hipError_t e = hipMalloc(&b->p, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(program scratch)");
+    b->refs = 1;
+    *out = b.get();
+    g_bufs.push_back(std::move(b));
+    return STENCIL_OK;
+}
+
+// Drops an entry: waits for its stream (launches in flight may still use the
+// graph and the scratch), then frees the graph and, with its last user, the
+// scratch buffer.
+void entry_release(Entry &en) {
+    int cur = 0;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    if (have_cur && cur != en.dev) hipSetDevice(en.dev);
+    hipStreamSynchronize(en.st);
+    if (en.exec) hipGraphExecDestroy(en.exec);
+    if (en.graph) hipGraphDestroy(en.graph);
+    en.exec = nullptr;
+    en.graph = nullptr;
+    if (en.buf && --en.buf->refs == 0) {
+        hipFree(en.buf->p);
+        for (size_t q = 0; q < g_bufs.size(); ++q)
+            if (g_bufs[q].get() == en.buf) {
+                g_bufs.erase(g_bufs.begin() + static_cast<long>(q));
+                break;
+            }
+    }
+    en.buf = nullptr;
+    if (have_cur && cur != en.dev) hipSetDevice(cur);
 }
 
 int check_program(const stencil_program_t *prog, int *dtype_out) {
@@ -415,15 +486,22 @@ int autotune(const stencil_program_t *prog, int dtype, char *scratch, hipStream_
 
 void program_release_all() {
     std::lock_guard<std::mutex> lock(g_mu);
-    if (!g_cache.empty()) hipDeviceSynchronize();
-    for (auto &kv : g_cache) {
-        Entry &en = *kv.second;
-        if (en.exec) hipGraphExecDestroy(en.exec);
-        if (en.graph) hipGraphDestroy(en.graph);
-        if (en.scratch) hipFree(en.scratch);
-    }
-    g_cache.clear();
+    for (auto &en : g_lru) entry_release(*en);
+    g_lru.clear();
+    for (auto &b : g_bufs)
+        if (b->p) hipFree(b->p);
+    g_bufs.clear();
 }
+
+long long program_held_bytes(int *programs) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    long long n = 0;
+    for (auto &b : g_bufs) n += static_cast<long long>(b->bytes);
+    if (programs) *programs = static_cast<int>(g_lru.size());
+    return n;
+}
+
+int stream_capturing(hipStream_t st, bool *capturing);
 
 }  // namespace stl
 
@@ -432,35 +510,63 @@ using namespace stl;
 STENCIL_API int stencil_program_run(const stencil_program_t *prog, void *stream) {
     int dtype = 0;
     TRY(check_program(prog, &dtype));
+    bool work = false;
+    for (int s = 0; s < prog->nsub; ++s)
+        work |= prog->sub[s].nfields > 0 && !empty(&prog->sub[s].coeff);
+    if (!work) return STENCIL_OK;  // nothing to run: no allocation, no launch
     hipStream_t st = static_cast<hipStream_t>(stream);
-    // Capture needs a real stream; on the null stream the program runs eagerly.
-    const bool graph = (prog->flags & STENCIL_PROGRAM_GRAPH) && st != nullptr;
+    bool capturing = false;
+    TRY(stream_capturing(st, &capturing));
+    // Capture needs a real stream; on the null stream the program runs
+    // eagerly.  Inside the caller's own capture the kernels are enqueued
+    // into it directly.
+    const bool graph = (prog->flags & STENCIL_PROGRAM_GRAPH) && st != nullptr && !capturing;
     const bool tune = (prog->flags & STENCIL_PROGRAM_AUTOTUNE) != 0;
-    const uint64_t key = signature(prog, st);
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return hip_fail(he, "hipGetDevice");
+    std::vector<unsigned char> key = signature(prog, dev, st);
+    const uint64_t hash = fnv(1469598103934665603ULL, key.data(), key.size());
 
     std::lock_guard<std::mutex> lock(g_mu);
-    auto it = g_cache.find(key);
-    if (it == g_cache.end()) {
+    auto it = g_lru.begin();
+    for (; it != g_lru.end(); ++it)
+        if ((*it)->hash == hash && (*it)->key == key) break;
+    if (it != g_lru.end()) {
+        g_lru.splice(g_lru.begin(), g_lru, it);  // most recently used first
+    } else {
+        if (capturing)
+            return fail(STENCIL_E_UNSUPPORTED,
+                        "the first run of a program allocates its scratch%s; run it once before capturing the "
+                        "stream",
+                        tune ? " and synchronises to autotune" : "");
         std::unique_ptr<Entry> en(new Entry);
+        en->key = std::move(key);
+        en->hash = hash;
+        en->dev = dev;
+        en->st = st;
         Plan sizing;
         build_plan(prog, dtype, 2, nullptr, &sizing);
-        if (sizing.scratch_bytes) {
-            hipError_t e = hipMalloc(&en->scratch, sizing.scratch_bytes);
-            if (e != hipSuccess) return hip_fail(e, "hipMalloc(program scratch)");
+        // Make room first, so that an evicted entry's scratch can be reused.
+        while (g_lru.size() >= PROGRAM_CACHE_MAX) {
+            entry_release(*g_lru.back());
+            g_lru.pop_back();
         }
+        TRY(buffer_get(dev, st, sizing.scratch_bytes, &en->buf));
+        char *scratch = en->buf ? static_cast<char *>(en->buf->p) : nullptr;
         const std::vector<Variant> cands = variants_for(dtype);
         en->var = cands.front();
         if (tune && cands.size() > 1) {
-            const int rc = autotune(prog, dtype, static_cast<char *>(en->scratch), st, &en->var);
+            const int rc = autotune(prog, dtype, scratch, st, &en->var);
             if (rc != STENCIL_OK) {
-                if (en->scratch) hipFree(en->scratch);
+                entry_release(*en);
                 return rc;
             }
         }
-        build_plan(prog, dtype, en->var.tj, static_cast<char *>(en->scratch), &en->plan);
-        it = g_cache.emplace(key, std::move(en)).first;
+        build_plan(prog, dtype, en->var.tj, scratch, &en->plan);
+        g_lru.push_front(std::move(en));
     }
-    Entry &en = *it->second;
+    Entry &en = *g_lru.front();
     if (!graph) {
         const hipError_t e = enqueue(en.plan, en.var, st);
         return e == hipSuccess ? STENCIL_OK : hip_fail(e, "program kernels");

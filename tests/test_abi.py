@@ -27,7 +27,7 @@ if _torch.cuda.is_available():
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(stencil_\w+)\s*\(", text,
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|void|const char \*)\s*(stencil_\w+)\s*\(", text,
                                  re.M)))
 
 
@@ -320,3 +320,55 @@ def test_program_validation():
     assert run_program(p) == 5
     p, keep = program(nsub=0)
     assert run_program(p) == 0                       # an empty program is a no-op
+
+
+# ---- spans of 2 GiB and more ---------------------------------------------------
+
+def far(n, **kw):
+    """n descriptors 64 GiB apart (room for the largest spans below)."""
+    return [fd(origin=FAKE + q * (1 << 36), **kw) for q in range(n)]
+
+
+@pytest.mark.parametrize("dtype,ni,nj,nk", [
+    (0, 1024, 1024, 520),    # FP64, 4.4 GB
+    (0, 1400, 1400, 1000),   # FP64, 15.9 GB
+    (1, 1024, 1024, 1050),   # FP32, 4.5 GB
+    (1, 1400, 1400, 1000),   # FP32, 7.9 GB
+    (1, 1024, 1024, 600),    # FP32, 2.6 GB
+    (2, 2000, 2000, 300),    # bf16, 2.4 GB
+])
+def test_hdiff_spans_beyond_the_inline_kernels_buffers(dtype, ni, nj, nk):
+    # Element offsets fit in 32 bits, byte offsets do not: the inlined kernel
+    # (raw buffers of < 2^31 bytes) must not run.  Asked for explicitly it is
+    # refused; by default the unfused kernels take the call, which here (no
+    # device) fails in the runtime before any launch rather than in the
+    # inlined kernel's launch.
+    u, c, o = far(3, dtype=dtype, ni=ni, nj=nj, nk=nk)
+    span = ((ni + 3) + (nj + 3) * u.sj + (nk - 1) * u.sk + 1) * (8, 4, 2)[dtype]
+    assert (ni + 3) + (nj + 3) * u.sj + (nk - 1) * u.sk < 2 ** 31 <= span
+    assert hdiff(u, c, o, B.config(level=2)) == 7
+    assert "below 2 GiB" in B.stencil_last_error()
+    assert hdiff(u, c, o, B.config(unroll=4, level=2)) == 7
+    rc = hdiff(u, c, o)
+    assert rc == 8 and "hdiff kernel" not in B.stencil_last_error(), B.stencil_last_error()
+
+
+def test_fused_spans_beyond_the_column_kernels_buffers():
+    fs = far(7, dtype=0, ni=3000, nj=3000, nk=40)   # FP64, 2.9 GB per field
+    r = ctypes.byref
+    assert B.lib().stencil_hdiff_vadv(*[r(f) for f in fs[:6]], 10.0, r(fs[6]), r(B.config(level=2)),
+                                      None) == 7
+    assert adjoint_far(far(10, dtype=1, ni=3000, nj=3000, nk=80)) == 7
+
+
+def adjoint_far(fs):
+    r = ctypes.byref
+    return B.lib().stencil_hdiff_vadv_adjoint(*[r(f) for f in fs[:6]], 10.0, r(fs[6]), r(fs[7]), r(fs[8]),
+                                              r(fs[9]), None, None, None, None, None, None)
+
+
+def test_held_memory_starts_empty():
+    n = ctypes.c_int32(-1)
+    assert B.lib().stencil_held_memory(ctypes.byref(n)) == 0
+    assert n.value == 0
+    assert B.lib().stencil_held_memory(None) == 0

@@ -141,13 +141,16 @@ def test_matrix_gradients_match_oracle(dtype, shape):
         assert np.all(full[:, :2] == -7.0) and np.all(full[:, :, :2] == -7.0)
 
 
-def test_adjoint_against_central_differences():
+@pytest.mark.parametrize("shape", [(96, 40, 80), (256, 256, 80)])
+def test_adjoint_against_central_differences(shape):
     # FP64 forward on the GPU, eps = 1e-6: L is piecewise linear in u and
     # linear in coeff and wcon, so central differences are exact up to
     # rounding away from limiter switches; probes that move a decision are
     # skipped.  The loss difference is summed in FP64 over all points (only
-    # the few columns a probe touches differ).
-    ni, nj, nk = 96, 40, 80
+    # the few columns a probe touches differ).  256 x 256 x 80 is the
+    # reverse-mode workload itself.
+    ni, nj, nk = shape
+    note("central differences at %dx%dx%d" % shape)
     f, g = setup(ni, nj, nk, "f64", SEED + 52)
     out = gpu_matrix_adjoint(g, "f64", gpu_forward(g))
     grads = {n: out["g" + n].to_numpy() for n in ("u", "coeff", "wcon", "a", "b", "c")}
@@ -233,3 +236,41 @@ def test_torch_gradcheck_small():
 
     inputs_ = tuple(t.buf.detach().clone().requires_grad_(True) for t in (u, g["coeff"], g["wcon"]))
     assert torch.autograd.gradcheck(fn, inputs_, eps=1e-6, atol=1e-8, rtol=1e-6, fast_mode=True)
+
+
+def test_adjoint_inside_a_captured_graph():
+    """After one call on a stream has sized its scratch, the reverse pass
+    captures into a graph and replays; a larger call under capture, which
+    would have to grow the scratch, is refused instead of allocating."""
+    ni, nj, nk = 70, 12, 40
+    f, g = setup(ni, nj, nk, "f32", SEED + 55)
+    s_cap = torch.cuda.Stream()
+    ref = gpu_adjoint(g, "f32")
+    out = {n: g["u"].like(fill=0.0) for n in ("gu", "gcoeff", "gwcon")}
+
+    def call():
+        B.stencil_hdiff_vadv_adjoint(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT, g["w"],
+                                     out["gu"], out["gcoeff"], out["gwcon"])
+
+    with torch.cuda.stream(s_cap):
+        call()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s_cap):
+        call()
+    for rep in range(3):
+        for t in out.values():
+            t.buf.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for n in out:
+            assert np.array_equal(out[n].to_numpy(), ref[n].to_numpy()), (rep, n)
+    f2, g2 = setup(2 * ni, 2 * nj, nk, "f32", SEED + 56)
+    out2 = {n: g2["u"].like(fill=0.0) for n in ("gu", "gcoeff", "gwcon")}
+    graph2 = torch.cuda.CUDAGraph()
+    with pytest.raises(B.StencilError) as e:
+        with torch.cuda.graph(graph2, stream=s_cap):
+            B.stencil_hdiff_vadv_adjoint(g2["u"], g2["coeff"], g2["wcon"], g2["a"], g2["b"], g2["c"], DT,
+                                         g2["w"], out2["gu"], out2["gcoeff"], out2["gwcon"])
+    assert e.value.status == "E_UNSUPPORTED"

@@ -82,14 +82,14 @@ def test_program_stage_chains(dtype, stages):
 
 def test_config4_six_subdomains_eight_fields():
     """hdiff -> vadv -> vdiff -> hgrad on 8 fields over the 6 uneven
-    subdomains (96x96x60 .. 384x256x90), FP32, graph + autotune."""
+    subdomains (96x96x60 .. 384x256x90), FP32, graph + autotune; every field
+    of every subdomain against the oracle."""
     data = inputs.batched(storage="f32")
     subs = device_program(data, "f32")
     run(subs, FULL, flags=B.PROGRAM_GRAPH | B.PROGRAM_AUTOTUNE)
     worst = 0.0
     for s_idx, (d, s) in enumerate(zip(data, subs)):
-        fields = range(8) if s_idx < 4 else (0, 7)
-        for f in fields:
+        for f in range(8):
             got = s["z"][f].to_numpy(interior=True)
             e = normwise(got, reference(d, f, FULL))
             worst = max(worst, e)
@@ -164,3 +164,74 @@ def test_program_outputs_leave_halos_alone():
     run(subs, FULL)
     for s in subs:
         assert halo_untouched(s["z"][0])
+
+
+def test_program_cache_is_bounded_and_shares_scratch():
+    """Forty programs that differ only in their output pointers: the cache
+    keeps the 16 most recent, they share one scratch buffer, and a program
+    that was evicted runs again with the same result."""
+    data = small_data("f32", nfields=2, shapes=((70, 13, 9), (40, 33, 17)))
+    subs = device_program(data, "f32")
+    B.stencil_shutdown()
+    assert B.stencil_held_memory() == (0, 0)
+    run(subs, FULL)
+    ref = [[z.to_numpy() for z in s["z"]] for s in subs]
+    held1, n1 = B.stencil_held_memory()
+    assert n1 == 1 and held1 > 0
+    outs = []
+    for q in range(40):
+        z = [[B.Field.empty(*d["shape"], d["halo"], "f32", fill=-7.0) for _ in d["u"]] for d in data]
+        alt = [dict(s, z=zz) for s, zz in zip(subs, z)]
+        run(alt, FULL, flags=B.PROGRAM_GRAPH if q % 2 else 0)
+        outs.append(z)
+        held, n = B.stencil_held_memory()
+        assert n == min(q + 2, 16) and held == held1, (q, n, held, held1)
+    for s in subs:
+        for z in s["z"]:
+            z.buf.fill_(-7.0)
+    run(subs, FULL)  # evicted long ago: planned again
+    for s, r in zip(subs, ref):
+        for z, rr in zip(s["z"], r):
+            assert np.array_equal(z.to_numpy(), rr)
+    for z in outs:
+        for zz, r in zip(z, ref):
+            for a, b in zip(zz, r):
+                assert np.array_equal(a.to_numpy(), b)
+
+
+def test_program_inside_a_captured_graph():
+    """A program already run on a stream is enqueued into that stream's
+    capture (no allocation, no nested capture); a program never run there is
+    refused under capture instead of allocating."""
+    data = small_data("f32", nfields=2)
+    subs = device_program(data, "f32")
+    run(subs, FULL)
+    ref = [[z.to_numpy() for z in s["z"]] for s in subs]
+    s_cap = torch.cuda.Stream()
+    spec = B.ProgramSpec(subs, stages=FULL, dt=DT, kappa=KAPPA, beta_h=BH, beta_v=BV,
+                         flags=B.PROGRAM_GRAPH | B.PROGRAM_AUTOTUNE)
+    with torch.cuda.stream(s_cap):
+        B.stencil_program_run(spec)          # first run on this stream: plans, tunes, allocates
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s_cap):
+        B.stencil_program_run(spec)
+    for rep in range(4):
+        for s in subs:
+            for z in s["z"]:
+                z.buf.fill_(-7.0)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for s, r in zip(subs, ref):
+            for z, rr in zip(s["z"], r):
+                assert np.array_equal(z.to_numpy(), rr), rep
+    other = B.ProgramSpec(subs, stages=B.STAGE_HDIFF | B.STAGE_VADV | B.STAGE_VDIFF, dt=DT, kappa=KAPPA,
+                          beta_h=BH, beta_v=BV)
+    g2 = torch.cuda.CUDAGraph()
+    with pytest.raises(B.StencilError) as e:
+        with torch.cuda.graph(g2, stream=s_cap):
+            B.stencil_program_run(other)
+    assert e.value.status == "E_UNSUPPORTED"
