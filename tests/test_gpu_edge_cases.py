@@ -3,6 +3,10 @@
 * A constant u: every Laplacian and flux is 0, so h = u exactly.
 * u = s (i^4 + j^4) (s a power of two): every flux is kept (flx * du < 0 at
   every face) and h = u + 48 s coeff, exact in FP64 for coeff held in 24 bits.
+  Its grid is 70 x 70 (still two tiles in i, the second ragged) so that 4u,
+  and with it every partial sum of the Laplacian in any evaluation order,
+  stays below 2^24 units of s: the stencil arithmetic is then exact in FP32
+  too, and only the final update rounds.
 * Unit spikes: h follows the hand-derived fixture tests/golden/hdiff_spike.txt
   exactly, including the fluxes that sit on a limiter tie (product exactly 0,
   kept).  Spikes sit on tile seams, at the ragged edges and in the halo.
@@ -29,7 +33,8 @@ if not torch.cuda.is_available():
 from paper_2005_13014_amd import binding as B  # noqa: E402
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-NI, NJ, NK, H = 100, 70, 6, 2          # two 64-wide tiles (the second ragged), ragged rows
+NI, NJ, NK, H = 100, 70, 10, 2         # two 64-wide tiles (the second ragged), ragged rows;
+                                        # nk >= 8 for the four-lanes-per-column schedule
 LEVELS = {"original": B.config(level=1), "u1": B.config(unroll=1), "u2": B.config(unroll=2),
           "u4": B.config(unroll=4)}
 SPIKES = [(0, 0), (NI - 1, NJ - 1), (63, 8), (64, 17), (-2, 30), (NI + 1, 44), (30, -1), (50, NJ + 1),
@@ -46,34 +51,44 @@ def spike_rows():
         return [[int(v) for v in ln.split()] for ln in fh if ln.strip() and not ln.lstrip().startswith("#")]
 
 
-def grid():
-    k, j, i = np.meshgrid(np.arange(NK), np.arange(-H, NJ + H), np.arange(-H, NI + H), indexing="ij")
+NI_QUARTIC = 70
+
+
+def dims(case):
+    """Interior extents (ni, nj, nk) of a case."""
+    return (NI_QUARTIC if case == "quartic" else NI), NJ, NK
+
+
+def grid(ni, nj, nk):
+    k, j, i = np.meshgrid(np.arange(nk), np.arange(-H, nj + H), np.arange(-H, ni + H), indexing="ij")
     return k, j, i
 
 
 def case_inputs(case):
     """Padded u and coeff (float64 holding values exact in every storage type)
     and the closed-form h on the interior."""
+    ni, nj, nk = dims(case)
     rng = np.random.default_rng(SEED + 900)
-    shape = (NK, NJ + 2 * H, NI + 2 * H)
+    shape = (nk, nj + 2 * H, ni + 2 * H)
     coeff = inputs.round_to(rng.uniform(0.0, 0.1, shape), "bf16")
     if case == "constant":
         u = np.full(shape, 0.375)
         h = u[:, H:-H, H:-H].copy()
     elif case == "quartic":
-        _, j, i = grid()
-        u = SCALE * ((i - 50.0) ** 4 + (j - 35.0) ** 4)
+        _, j, i = grid(ni, nj, nk)
+        u = SCALE * ((i - 35.0) ** 4 + (j - 35.0) ** 4)
+        assert 4 * u.max() / SCALE < 2 ** 24
         h = (u + 48.0 * SCALE * coeff)[:, H:-H, H:-H]
     else:
         c = 2.0 ** -4
         coeff = np.full(shape, c)
         u = np.zeros(shape)
-        h = np.zeros((NK, NJ, NI))
+        h = np.zeros((nk, nj, ni))
         for si, sj in SPIKES:
             u[:, sj + H, si + H] = 1.0
             for di, dj, base, mult in spike_rows():
                 i, j = si + di, sj + dj
-                if 0 <= i < NI and 0 <= j < NJ:
+                if 0 <= i < ni and 0 <= j < nj:
                     h[:, j, i] += base + mult * c
         # the spikes are at least 6 cells apart in i or j: no two diamonds meet
         for p in range(len(SPIKES)):
@@ -94,10 +109,11 @@ def test_hdiff_closed_forms(dtype, case, level):
         pytest.skip("i^4 + j^4 is not exact in bfloat16")
     note("closed form", case, dtype, level)
     u, coeff, h = case_inputs(case)
+    ni, nj, nk = dims(case)
     assert exact_in(u, dtype) and exact_in(coeff, dtype)
     gu = B.Field.from_numpy(u, H, dtype)
     gc = B.Field.from_numpy(coeff, H, dtype)
-    out = B.Field.empty(NI, NJ, NK, H, dtype, fill=-7.0)
+    out = B.Field.empty(ni, nj, nk, H, dtype, fill=-7.0)
     B.stencil_hdiff(gu, gc, out, cfg=LEVELS[level])
     torch.cuda.synchronize()
     got = out.to_numpy(interior=True)
@@ -105,8 +121,9 @@ def test_hdiff_closed_forms(dtype, case, level):
         # constant and spikes everywhere; quartic in FP64
         assert np.array_equal(got, h), np.abs(got - h).max()
     else:
-        # quartic in FP32: the closed form rounded once (fused multiply-add),
-        # or twice where the product is rounded first
+        # quartic in FP32: every Laplacian, flux and coeff * divergence is
+        # exact (coeff has 8 significant bits, 48 s two); only u + that
+        # product rounds
         ulp = np.spacing(np.abs(h).astype(np.float32)).astype(np.float64)
         assert np.all(np.abs(got - h) <= ulp), np.abs((got - h) / ulp).max()
     assert halo_untouched(out)
@@ -118,10 +135,11 @@ def test_hdiff_closed_forms(dtype, case, level):
 def test_fused_closed_forms(dtype, case, schedule):
     note("fused closed form", case, dtype, "schedule", schedule)
     u, coeff, h = case_inputs(case)
-    f = inputs.fields(NI, NJ, NK, H, seed=SEED + 901, storage=dtype)
+    ni, nj, nk = dims(case)
+    f = inputs.fields(ni, nj, nk, H, seed=SEED + 901, storage=dtype)
     f["u"], f["coeff"] = u, coeff
     g = {n: B.Field.from_numpy(f[n], H, dtype) for n in ("u", "coeff", "wcon", "a", "b", "c")}
-    x = B.Field.empty(NI, NJ, NK, H, dtype, fill=-7.0)
+    x = B.Field.empty(ni, nj, nk, H, dtype, fill=-7.0)
     cfg = B.config(schedule=schedule) if schedule else None
     B.stencil_hdiff_vadv(g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT, x, cfg=cfg)
     torch.cuda.synchronize()
