@@ -38,7 +38,8 @@
  *          stencil_hdiff_vadv_adjoint -- when they need more scratch than the
  *          stream's buffer holds (the first such call on a stream, or a
  *          larger one): the stream is synchronised, the old buffer freed and
- *          a larger one allocated;
+ *          a larger one allocated (stencil_hdiff_vadv_adjoint_noalloc, on
+ *          fixed scratch, never does);
  *      (2) stencil_program_run on the first run of a program signature: it
  *          allocates the program's scratch (shared with cached programs of
  *          the same size on the same stream), with STENCIL_PROGRAM_AUTOTUNE
@@ -200,6 +201,28 @@ int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stencil_field_t *
                                const stencil_field_t *x, const stencil_field_t *ga,
                                const stencil_field_t *gb, const stencil_field_t *gc,
                                const stencil_config_t *cfg, void *stream);
+
+/* stencil_hdiff_vadv_adjoint for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results, but the scratch is a
+ * fixed array of 128 MiB (134217728 bytes) inside the library's code object
+ * instead of a growing per-stream buffer, so the call never allocates, frees
+ * or synchronises.  Each device the library runs on holds its own copy of
+ * the array until the process ends.  The scratch a call needs is one
+ * field-sized plane of the compute type (FP64 storage: two), 256-byte
+ * aligned per plane (256x256x80 FP64 or 512x512x80 FP32 with a halo of 2
+ * fit); a larger call returns STENCIL_E_UNSUPPORTED before anything is
+ * enqueued.  All calls on one device share that device's array: calls that
+ * overlap in time on one device (on different streams, or from different
+ * threads without ordering) race on it and their results are undefined. */
+int stencil_hdiff_vadv_adjoint_noalloc(const stencil_field_t *u, const stencil_field_t *coeff,
+                                       const stencil_field_t *wcon, const stencil_field_t *a,
+                                       const stencil_field_t *b, const stencil_field_t *c, double dt,
+                                       const stencil_field_t *w, const stencil_field_t *gu,
+                                       const stencil_field_t *gcoeff, const stencil_field_t *gwcon,
+                                       const stencil_field_t *x, const stencil_field_t *ga,
+                                       const stencil_field_t *gb, const stencil_field_t *gc,
+                                       const stencil_config_t *cfg, void *stream);
 
 /* Forward mode of stencil_hdiff_vadv: the tangent dx = J v in the direction
  * v = (du, dcoeff, dwcon, da, db, dc), with the limiter decisions of the

@@ -75,6 +75,8 @@ _SIGNATURES = {
     "stencil_hdiff_vadv": [_P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _C, _V],
     "stencil_hdiff_vadv_adjoint": [_P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P, _P,
                                    _P, _P, _C, _V],
+    "stencil_hdiff_vadv_adjoint_noalloc": [_P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P,
+                                           _P, _P, _P, _C, _V],
     "stencil_hdiff_vadv_jvp": [_P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P, _P, _P, _P,
                                _C, _V],
     "stencil_program_run": [ctypes.POINTER(Program), _V],
@@ -256,6 +258,16 @@ def stencil_hdiff_vadv_adjoint(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon
     """Reverse mode of x = vadv(hdiff(u)) for the loss sum(w * x): gu, gcoeff,
     gwcon, and with the forward result x also any of ga, gb, gc."""
     _check(lib().stencil_hdiff_vadv_adjoint(
+        _desc(u), _desc(coeff), _desc(wcon), _desc(a), _desc(b), _desc(c), float(dt), _desc(w),
+        _desc(gu), _desc(gcoeff), _desc(gwcon), _desc(x), _desc(ga), _desc(gb), _desc(gc), _cfg(cfg),
+        _stream(stream)))
+
+
+def stencil_hdiff_vadv_adjoint_noalloc(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon, x=None, ga=None,
+                                       gb=None, gc=None, cfg=None, stream=None):
+    """stencil_hdiff_vadv_adjoint through the entry point that allocates
+    nothing (fixed device scratch of 128 MiB per device)."""
+    _check(lib().stencil_hdiff_vadv_adjoint_noalloc(
         _desc(u), _desc(coeff), _desc(wcon), _desc(a), _desc(b), _desc(c), float(dt), _desc(w),
         _desc(gu), _desc(gcoeff), _desc(gwcon), _desc(x), _desc(ga), _desc(gb), _desc(gc), _cfg(cfg),
         _stream(stream)))

@@ -18,6 +18,9 @@
 //      through LDS, give gu on the interior and its 2-cell ring and
 //      gcoeff = -gh (flx - flx(i-1) + fly - fly(j-1)) on the interior.
 #include <algorithm>
+#include <cstdint>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "column.hpp"
@@ -541,6 +544,41 @@ static hipError_t adjoint_run(AdjArgs a, void *scratch, hipStream_t st) {
     hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a, nbi,
                        static_cast<int>(tiles), kc);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch for the reverse pass that allocates nothing
+// (stencil_hdiff_vadv_adjoint_noalloc).  The array is part of the code
+// object: every device the library runs on holds its own copy, at its own
+// address, until the process ends.  Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in for the symbol); it looks up
+// each device's address once, with that device current, and uses that.
+// Nothing in it needs to start at zero: the column kernel writes gh (and the
+// FP64 hdiff kernel h) on the whole interior before any kernel reads it, and
+// the hdiff adjoint masks what it reads outside the interior.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char adjoint_scratch[ADJOINT_FIXED_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_fixed_mu;
+std::map<int, void *> g_fixed_ptr;  // device -> address of its adjoint_scratch
+}  // namespace
+
+hipError_t adjoint_fixed_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_fixed_mu);
+    auto it = g_fixed_ptr.find(dev);
+    if (it == g_fixed_ptr.end()) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(adjoint_scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr || reinterpret_cast<uintptr_t>(p) % 256 != 0) return hipErrorInvalidSymbol;
+        it = g_fixed_ptr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return hipSuccess;
 }
 
 hipError_t launch_adjoint(int dtype, const AdjointArgs &x, void *scratch, hipStream_t st) {

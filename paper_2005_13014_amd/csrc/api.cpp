@@ -503,15 +503,15 @@ STENCIL_API int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field
 namespace stl {
 
 // The reverse pass behind stencil_hdiff_vadv_adjoint and its variant that
-// allocates nothing: fixed == nullptr takes the (device, stream) scratch
-// buffer (which may grow), otherwise `fixed` (fixed_bytes long) is used and
-// a call that needs more is refused.
+// allocates nothing: without `fixed` it takes the (device, stream) scratch
+// buffer (which may grow); with it, the fixed device array of
+// ADJOINT_FIXED_SCRATCH_BYTES, and a call that needs more is refused before
+// anything touches the device.
 int adjoint_entry(const stencil_field_t *u, const stencil_field_t *coeff, const stencil_field_t *wcon,
                   const stencil_field_t *a, const stencil_field_t *b, const stencil_field_t *c, double dt,
                   const stencil_field_t *w, const stencil_field_t *gu, const stencil_field_t *gcoeff,
                   const stencil_field_t *gwcon, const stencil_field_t *xf, const stencil_field_t *ga,
-                  const stencil_field_t *gb, const stencil_field_t *gc, void *stream, void *fixed,
-                  size_t fixed_bytes) {
+                  const stencil_field_t *gb, const stencil_field_t *gc, void *stream, bool fixed) {
     // Inputs first, outputs last (the alias check takes the last nout as outputs).
     const stencil_field_t *fs[15];
     const char *names[15];
@@ -556,11 +556,15 @@ int adjoint_entry(const stencil_field_t *u, const stencil_field_t *coeff, const 
     x.dt = dt;
     const size_t need = adjoint_scratch_bytes(u->dtype, x.sk, x.K);
     if (fixed) {
-        if (need > fixed_bytes)
+        if (need > ADJOINT_FIXED_SCRATCH_BYTES)
             return fail(STENCIL_E_UNSUPPORTED,
-                        "the call needs %zu bytes of scratch; the fixed scratch array holds %zu", need,
-                        fixed_bytes);
-        return launch_status(launch_adjoint(u->dtype, x, fixed, st), "adjoint kernels");
+                        "the call needs %zu bytes of scratch; the fixed scratch array of the entry point that "
+                        "allocates nothing holds %zu",
+                        need, static_cast<size_t>(ADJOINT_FIXED_SCRATCH_BYTES));
+        void *p = nullptr;
+        const hipError_t e = adjoint_fixed_scratch(&p);
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(adjoint scratch)");
+        return launch_status(launch_adjoint(u->dtype, x, p, st), "adjoint kernels");
     }
     ScratchLease lease;
     TRY(scratch_get(st, need, &lease));
@@ -579,7 +583,20 @@ STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stenc
                                            const stencil_field_t *gc, const stencil_config_t *cfg,
                                            void *stream) {
     (void)cfg;
-    return adjoint_entry(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon, xf, ga, gb, gc, stream, nullptr, 0);
+    return adjoint_entry(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon, xf, ga, gb, gc, stream, false);
+}
+
+STENCIL_API int stencil_hdiff_vadv_adjoint_noalloc(const stencil_field_t *u, const stencil_field_t *coeff,
+                                                   const stencil_field_t *wcon, const stencil_field_t *a,
+                                                   const stencil_field_t *b, const stencil_field_t *c,
+                                                   double dt, const stencil_field_t *w,
+                                                   const stencil_field_t *gu, const stencil_field_t *gcoeff,
+                                                   const stencil_field_t *gwcon, const stencil_field_t *xf,
+                                                   const stencil_field_t *ga, const stencil_field_t *gb,
+                                                   const stencil_field_t *gc, const stencil_config_t *cfg,
+                                                   void *stream) {
+    (void)cfg;
+    return adjoint_entry(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon, xf, ga, gb, gc, stream, true);
 }
 
 STENCIL_API int stencil_hdiff_vadv_jvp(const stencil_field_t *u, const stencil_field_t *coeff,

@@ -100,6 +100,11 @@ struct JvpArgs {
 constexpr int KMAX_JVP = 96;
 hipError_t launch_jvp(int dtype, const JvpArgs &a, hipStream_t st);
 hipError_t launch_adjoint(int dtype, const AdjointArgs &a, void *scratch, hipStream_t st);
+// The fixed scratch of the reverse pass that allocates nothing: a device
+// array of ADJOINT_FIXED_SCRATCH_BYTES in the code object; *out receives the
+// current device's address of it (looked up once per device).
+constexpr size_t ADJOINT_FIXED_SCRATCH_BYTES = size_t(128) << 20;
+hipError_t adjoint_fixed_scratch(void **out);
 
 // Streaming copy used as the bandwidth probe (probe.hip).
 hipError_t launch_probe_copy(const void *src, void *dst, long long nbytes, hipStream_t st);

@@ -113,6 +113,25 @@ def test_adjoint_matrix_gradient_checks():
     assert adjoint(empty[:10], x=empty[10], ga=empty[11], gb=empty[12], gc=empty[13]) == 0
 
 
+def adjoint_noalloc(fs, dt=10.0):
+    r = ctypes.byref
+    return B.lib().stencil_hdiff_vadv_adjoint_noalloc(*[r(f) for f in fs[:6]], dt, *[r(f) for f in fs[6:10]],
+                                                      None, None, None, None, None, None)
+
+
+def test_noalloc_adjoint_limit_is_checked_on_the_host():
+    # The fixed scratch holds 128 MiB: FP64 at 512 x 512 x 80 (two planes of
+    # about 170 MB) is refused before anything touches a device; the same
+    # validation as the scratch entry point comes first.
+    sj = 516
+    big = [fd(origin=FAKE + q * (1 << 36), dtype=0, ni=512, nj=512, nk=80, sj=sj, sk=sj * 516) for q in range(10)]
+    assert adjoint_noalloc(big) == 7
+    assert "fixed scratch" in B.stencil_last_error()
+    assert adjoint_noalloc(spaced(10, nk=97)) == 7
+    assert adjoint_noalloc(spaced(10)[:9] + [fd(origin=FAKE + 64)]) == 6
+    assert adjoint_noalloc(spaced(10, nk=0)) == 0
+
+
 def jvp(fs, x=None, du=None, dcoeff=None, dwcon=None, da=None, db=None, dc=None, dt=10.0):
     """fs: u, coeff, wcon, a, b, c, dx."""
     r = ctypes.byref
