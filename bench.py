@@ -561,8 +561,9 @@ def main():
                 summarize_variant(args.summarize_profiles, v, cal)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the stencil path runs on a single MI355X and no "
-              "multi-GPU halo exchange is built; run it with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the stencil path runs on a single MI355X (its "
+              "horizontal decomposition and halo exchange are emulated on that one device); run it "
+              "with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -326,6 +326,41 @@ int stencil_rtc_launch(void *handle, const uint32_t grid[3], const uint32_t bloc
 /* Unloads a compiled kernel; NULL is a no-op. */
 int stencil_rtc_release(void *handle);
 
+/* ---- horizontal domain decomposition ------------------------------------ */
+
+/* A grid split into px x py rectangles in (i, j) -- the shares that separate
+ * GPUs would own -- held here as separate halo-padded fields on one device.
+ * vadv and its Thomas solve are column-local; only horizontal diffusion reads
+ * across a share's edge, through the u halo whose width shape inference
+ * derives (Sec. V-B: 2 for hdiff, 3 for the timestep chain).  The paper
+ * itself runs on one GPU; the decomposition is this library's.
+ * shares: px * py descriptors, share (p, q) at shares[p + px q], p along i
+ * and q along j; share (p, q)'s interior follows share (p - 1, q)'s in i and
+ * share (p, q - 1)'s in j.  All shares have one dtype and nk; shares in one
+ * column p have the same ni, shares in one row q the same nj; strides may
+ * differ.  Shares must not overlap (STENCIL_E_ALIAS).  width: cells
+ * exchanged (1 <= width; every share's halo at least width wide and, where
+ * it has neighbours in that direction, its interior too).  1 <= px * py <= 64.
+ * The halo blocks on the outer boundary of the decomposition are never
+ * written: they hold the whole grid's halo data. */
+
+/* Fills each share's halo blocks toward its up to eight neighbours (edges and
+ * corners, width cells deep) with the neighbours' interior cells at the same
+ * grid position: afterwards every share holds, on its interior and halo, what
+ * the undivided grid holds there.  One launch on `stream`. */
+int stencil_halo_exchange(const stencil_field_t *shares, int32_t px, int32_t py, int32_t width,
+                          void *stream);
+
+/* The transpose of stencil_halo_exchange, for gradients: every interior cell
+ * that the exchange copies into neighbours' halos receives the sum of those
+ * halo cells (added to its own value, in a fixed order of directions, in the
+ * compute type).  Applied to per-share gradients with respect to u (interior
+ * plus halo ring, as stencil_hdiff_vadv_adjoint writes them), it yields the
+ * undivided grid's gradient on every share's interior, and on the outer
+ * boundary's halo cells.  Halos are read, not cleared.  One launch. */
+int stencil_halo_accumulate(const stencil_field_t *shares, int32_t px, int32_t py, int32_t width,
+                            void *stream);
+
 /* ---- library management and measurement --------------------------------- */
 
 /* Message describing the calling thread's last nonzero return code. */

@@ -80,6 +80,8 @@ _SIGNATURES = {
     "stencil_hdiff_vadv_jvp": [_P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P, _P, _P, _P,
                                _C, _V],
     "stencil_program_run": [ctypes.POINTER(Program), _V],
+    "stencil_halo_exchange": [ctypes.POINTER(FieldDesc), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _V],
+    "stencil_halo_accumulate": [ctypes.POINTER(FieldDesc), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _V],
     "stencil_rtc_compile": [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)],
     "stencil_rtc_launch": [_V, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
                            ctypes.POINTER(ctypes.c_void_p), _V],
@@ -306,6 +308,32 @@ def stencil_program_run(prog, stream=None):
     if isinstance(prog, ProgramSpec):
         prog = prog.struct
     _check(lib().stencil_program_run(ctypes.byref(prog), _stream(stream)))
+
+
+def _shares(shares, px, py):
+    """The descriptor array of px * py Fields given row-major (p fastest)."""
+    if len(shares) != px * py:
+        raise ValueError("%d shares for a %d x %d decomposition" % (len(shares), px, py))
+    arr = (FieldDesc * len(shares))()
+    for n, f in enumerate(shares):
+        if isinstance(f, FieldDesc):
+            arr[n] = f
+        else:
+            if f.buf.device.type != "cuda":
+                raise ValueError("fields must live in GPU memory")
+            arr[n] = f.desc()
+    return arr
+
+
+def stencil_halo_exchange(shares, px, py, width, stream=None):
+    """Fills the shares' halos from their neighbours' interiors (shares[p + px*q])."""
+    _check(lib().stencil_halo_exchange(_shares(shares, px, py), int(px), int(py), int(width), _stream(stream)))
+
+
+def stencil_halo_accumulate(shares, px, py, width, stream=None):
+    """Adds the shares' halo cells into the neighbours' interior cells they mirror."""
+    _check(lib().stencil_halo_accumulate(_shares(shares, px, py), int(px), int(py), int(width),
+                                         _stream(stream)))
 
 
 class ProgramSpec:

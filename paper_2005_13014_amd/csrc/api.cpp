@@ -648,6 +648,70 @@ STENCIL_API int stencil_hdiff_vadv_jvp(const stencil_field_t *u, const stencil_f
     return launch_status(launch_jvp(u->dtype, v, static_cast<hipStream_t>(stream)), "jvp kernel");
 }
 
+namespace stl {
+
+// Validation and launch shared by the halo exchange and its transpose.
+static int halo_entry(const stencil_field_t *shares, int px, int py, int width, void *stream, bool accumulate) {
+    if (!shares) return fail(STENCIL_E_NULL, "shares: array is NULL");
+    if (px < 1 || py < 1 || static_cast<long long>(px) * py > HALO_MAX_SHARES)
+        return fail(STENCIL_E_ARG, "px x py = %d x %d shares; 1 to %d are supported", px, py, HALO_MAX_SHARES);
+    if (width < 1) return fail(STENCIL_E_ARG, "halo width %d < 1", width);
+    const int n = px * py;
+    std::vector<const stencil_field_t *> fs(n);
+    std::vector<std::string> nm(n);
+    std::vector<const char *> names(n);
+    for (int s = 0; s < n; ++s) {
+        fs[s] = &shares[s];
+        nm[s] = "shares[" + std::to_string(s) + "]";
+        names[s] = nm[s].c_str();
+        TRY(check_field(fs[s], names[s]));
+    }
+    for (int s = 0; s < n; ++s) {
+        const stencil_field_t *f = fs[s], *r = fs[0];
+        const int p = s % px, q = s / px;
+        if (f->dtype != r->dtype)
+            return fail(STENCIL_E_DTYPE, "%s has dtype %d but shares[0] has %d", names[s], f->dtype, r->dtype);
+        if (f->nk != r->nk) return fail(STENCIL_E_SHAPE, "%s has nk=%d but shares[0] has %d", names[s], f->nk, r->nk);
+        if (f->ni != fs[p]->ni)
+            return fail(STENCIL_E_SHAPE, "%s has ni=%d but the share at the top of its column has %d", names[s],
+                        f->ni, fs[p]->ni);
+        if (f->nj != fs[q * px]->nj)
+            return fail(STENCIL_E_SHAPE, "%s has nj=%d but the first share of its row has %d", names[s], f->nj,
+                        fs[q * px]->nj);
+        if ((px > 1 && f->hi < width) || (py > 1 && f->hj < width))
+            return fail(STENCIL_E_HALO, "%s: halo (%d, %d) narrower than the exchanged width %d", names[s], f->hi,
+                        f->hj, width);
+        if (f->nk > 0 && ((px > 1 && f->ni < width) || (py > 1 && f->nj < width)))
+            return fail(STENCIL_E_SHAPE, "%s: interior %d x %d narrower than the exchanged width %d", names[s],
+                        f->ni, f->nj, width);
+    }
+    if (fs[0]->nk == 0 || n == 1) return STENCIL_OK;
+    // Every share is read by its neighbours and written: no two may overlap.
+    TRY(check_alias(fs.data(), names.data(), n, n));
+    HaloArgs a{};
+    for (int s = 0; s < n; ++s) a.s[s] = {shares[s].origin, shares[s].sj, shares[s].sk};
+    for (int p = 0; p < px; ++p) a.ni[p] = fs[p]->ni;
+    for (int q = 0; q < py; ++q) a.nj[q] = fs[q * px]->nj;
+    a.px = px;
+    a.py = py;
+    a.w = width;
+    a.K = fs[0]->nk;
+    return launch_status(launch_halo(fs[0]->dtype, a, accumulate, static_cast<hipStream_t>(stream)),
+                         accumulate ? "halo accumulate kernel" : "halo exchange kernel");
+}
+
+}  // namespace stl
+
+STENCIL_API int stencil_halo_exchange(const stencil_field_t *shares, int32_t px, int32_t py, int32_t width,
+                                      void *stream) {
+    return halo_entry(shares, px, py, width, stream, false);
+}
+
+STENCIL_API int stencil_halo_accumulate(const stencil_field_t *shares, int32_t px, int32_t py, int32_t width,
+                                        void *stream) {
+    return halo_entry(shares, px, py, width, stream, true);
+}
+
 STENCIL_API int stencil_probe_copy(const void *src, void *dst, int64_t nbytes, void *stream) {
     if (!src || !dst) return fail(STENCIL_E_NULL, "probe_copy: NULL pointer");
     if (nbytes < 0 || nbytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 ||

@@ -106,6 +106,22 @@ hipError_t launch_adjoint(int dtype, const AdjointArgs &a, void *scratch, hipStr
 constexpr size_t ADJOINT_FIXED_SCRATCH_BYTES = size_t(128) << 20;
 hipError_t adjoint_fixed_scratch(void **out);
 
+// Halo exchange between the shares of a horizontally decomposed grid and its
+// transpose (halo.hip).  Share (p, q) is s[p + px q]; its interior is ni[p] x
+// nj[q] x K; w is the halo width exchanged (every share's halo holds at
+// least w cells and every interior at least w).
+constexpr int HALO_MAX_SHARES = 64;
+struct HaloShare {
+    void *origin;
+    long long sj, sk;
+};
+struct HaloArgs {
+    HaloShare s[HALO_MAX_SHARES];
+    int ni[HALO_MAX_SHARES], nj[HALO_MAX_SHARES];
+    int px, py, w, K;
+};
+hipError_t launch_halo(int dtype, const HaloArgs &a, bool accumulate, hipStream_t st);
+
 // Streaming copy used as the bandwidth probe (probe.hip).
 hipError_t launch_probe_copy(const void *src, void *dst, long long nbytes, hipStream_t st);
 hipError_t launch_probe_read(const void *src, long long nbytes, unsigned key, void *sink, hipStream_t st);

@@ -386,6 +386,47 @@ def adjoint_far(fs):
                                               r(fs[9]), None, None, None, None, None, None)
 
 
+def halo(shares, px, py, width, accumulate=False):
+    arr = (B.FieldDesc * len(shares))(*shares)
+    fn = B.lib().stencil_halo_accumulate if accumulate else B.lib().stencil_halo_exchange
+    return fn(arr, px, py, width, None)
+
+
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_halo_exchange_validation(accumulate):
+    def shares(nis, njs, **kw):
+        out, n = [], 0
+        for nj in njs:
+            for ni in nis:
+                out.append(fd(origin=FAKE + n * (1 << 30), ni=ni, nj=nj, **kw))
+                n += 1
+        return out
+
+    ok = shares((16, 12, 9), (12, 7))
+    assert halo([], 0, 1, 2, accumulate) == 9
+    assert halo(shares((4,) * 9, (4,) * 8), 9, 8, 2, accumulate) == 9    # more than 64 shares
+    assert halo(ok, 3, 2, 0, accumulate) == 9                              # width < 1
+    assert halo(ok, 3, 2, 3, accumulate) == 5                              # halo 2 < width 3
+    bad = list(ok)
+    bad[4] = fd(origin=bad[4].origin, ni=13, nj=7)                         # ni differs within column 1
+    assert halo(bad, 3, 2, 2, accumulate) == 3
+    bad = list(ok)
+    bad[5] = fd(origin=bad[5].origin, ni=9, nj=8)                          # nj differs within row 1
+    assert halo(bad, 3, 2, 2, accumulate) == 3
+    bad = list(ok)
+    bad[2] = fd(origin=bad[2].origin, ni=9, nj=12, nk=4)                   # nk differs
+    assert halo(bad, 3, 2, 2, accumulate) == 3
+    bad = list(ok)
+    bad[3] = fd(origin=bad[3].origin, dtype=0, ni=16, nj=7)                # dtype differs
+    assert halo(bad, 3, 2, 2, accumulate) == 2
+    bad = list(ok)
+    bad[1] = fd(origin=ok[0].origin + 256, ni=12, nj=12)                   # overlapping shares
+    assert halo(bad, 3, 2, 2, accumulate) == 6
+    assert halo(shares((1, 12, 9), (12, 7)), 3, 2, 2, accumulate) == 3     # interior narrower than width
+    assert halo(shares((16, 12, 9), (12, 7), nk=0), 3, 2, 2, accumulate) == 0   # empty: no-op
+    assert halo(shares((16,), (12,)), 1, 1, 2, accumulate) == 0           # one share: nothing to exchange
+
+
 def test_held_memory_starts_empty():
     n = ctypes.c_int32(-1)
     assert B.lib().stencil_held_memory(ctypes.byref(n)) == 0
