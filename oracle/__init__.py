@@ -24,28 +24,67 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The same source built with OpenMP (its pragmas split the outermost loops of
+# the forward stages over threads; results are bitwise the same).  Used only
+# to time the oracle on all host cores.
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
-_lib = None
+_libs = {}
+_parallel = False
+
+
+def _compile(out, openmp):
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-Wall", "-Wextra"] + (["-fopenmp"] if openmp else ["-Wno-unknown-pragmas"]) + ["-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so (gcc, -O2, no FP contraction)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+    """Compile oracle.c into liboracle.so (gcc, -O2, no FP contraction) and,
+    with OpenMP, into liboracle_omp.so."""
+    for out, omp in ((_LIB, False), (_LIB_OMP, True)):
+        if force or not os.path.exists(out):
+            _compile(out, omp)
     return _LIB
 
 
+class parallel:
+    """Context in which the oracle functions run on all the threads OpenMP
+    gives them (OMP_NUM_THREADS, else every host core)."""
+
+    def __enter__(self):
+        global _parallel
+        self._old, _parallel = _parallel, True
+        return self
+
+    def __exit__(self, *exc):
+        global _parallel
+        _parallel = self._old
+        return False
+
+
+def threads():
+    """Threads the OpenMP build uses (1 for the plain build)."""
+    lib = ctypes.CDLL(_LIB_OMP) if os.path.exists(_LIB_OMP) else None
+    if lib is None:
+        return 1
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        return int(gomp.omp_get_max_threads())
+    except OSError:
+        return 1
+
+
 def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        _lib = ctypes.CDLL(_LIB)
-    return _lib
+    path = _LIB_OMP if _parallel else _LIB
+    lib = _libs.get(path)
+    if lib is None:
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            _compile(path, path == _LIB_OMP)
+        lib = _libs[path] = ctypes.CDLL(path)
+    return lib
 
 
 _D = ctypes.POINTER(ctypes.c_double)

@@ -27,6 +27,12 @@
  * cells in i and j ([-e, n+e)); inputs must then carry the halo the operator
  * reads (the access extents that shape inference derives, Sec. V-B).
  *
+ * Threads: the forward stages carry OpenMP pragmas on their outermost
+ * loop (levels for the horizontal stages, rows of columns for the column
+ * stages).  Every element is still computed by one thread with the same
+ * operations in the same order, so the results are bitwise the same for any
+ * thread count; built without -fopenmp (the default) the pragmas are ignored.
+ *
  * Readings where the paper is silent (it names these benchmarks but prints
  * no formula):
  *  - hdiff: lap = 4u - u(i+1) - u(i-1) - u(j+1) - u(j-1);
@@ -79,6 +85,7 @@ static int bad_dims(int ni, int nj, int nk)
 int oracle_lap(int ni, int nj, int nk, const double *u, int hu, double *lap, int hl, int e)
 {
     if (bad_dims(ni, nj, nk) || e < 0 || hu < e + 1 || hl < e) return ERR_ARG;
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < nk; ++k)
         for (int j = -e; j < nj + e; ++j)
             for (int i = -e; i < ni + e; ++i) {
@@ -100,6 +107,7 @@ int oracle_lap(int ni, int nj, int nk, const double *u, int hu, double *lap, int
 static void flux_i(int ni, int nj, int nk, const double *u, int hu, const double *lap, int hl,
                    double *flx, int hf, unsigned char *kept, const unsigned char *force_kept, int e)
 {
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < nk; ++k)
         for (int j = -e; j < nj + e; ++j)
             for (int i = -1 - e; i < ni + e; ++i) {
@@ -117,6 +125,7 @@ static void flux_i(int ni, int nj, int nk, const double *u, int hu, const double
 static void flux_j(int ni, int nj, int nk, const double *u, int hu, const double *lap, int hl,
                    double *fly, int hf, unsigned char *kept, const unsigned char *force_kept, int e)
 {
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < nk; ++k)
         for (int j = -1 - e; j < nj + e; ++j)
             for (int i = -e; i < ni + e; ++i) {
@@ -153,6 +162,7 @@ int oracle_hdiff_ex(int ni, int nj, int nk, const double *u, int hu, const doubl
     oracle_lap(ni, nj, nk, u, hu, lap, hl, e + 1);
     flux_i(ni, nj, nk, u, hu, lap, hl, flx, hf, kx, force_kx, e);
     flux_j(ni, nj, nk, u, hu, lap, hl, fly, hf, ky, force_ky, e);
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < nk; ++k)
         for (int j = -e; j < nj + e; ++j)
             for (int i = -e; i < ni + e; ++i) {
@@ -184,6 +194,7 @@ int oracle_rhs(int ni, int nj, int nk, const double *h, int hh, const double *w,
                double *d, int hd, int e)
 {
     if (bad_dims(ni, nj, nk) || e < 0 || hh < e || hw < e || hd < e) return ERR_ARG;
+#pragma omp parallel for schedule(static)
     for (int j = -e; j < nj + e; ++j)
         for (int i = -e; i < ni + e; ++i)
             for (int k = 0; k < nk; ++k) {
@@ -235,12 +246,17 @@ int oracle_thomas(int ni, int nj, int nk, const double *a, int ha, const double 
     if (bad_dims(ni, nj, nk) || e < 0 || ha < e || hb < e || hc < e || hd < e || hx < e)
         return ERR_ARG;
     if (nk == 0) return OK;
-    /* The column walker below needs one layout; copy each column out. */
-    double *col = (double *)malloc((size_t)nk * 7 * sizeof(double));
-    if (!col) return ERR_MEM;
-    double *ca = col, *cb = col + nk, *cc = col + 2 * nk, *cd = col + 3 * nk, *cx = col + 4 * nk,
-           *cp = col + 5 * nk, *dp = col + 6 * nk;
-    for (int j = -e; j < nj + e; ++j)
+    int failed = 0;
+#pragma omp parallel for schedule(static) reduction(| : failed)
+    for (int j = -e; j < nj + e; ++j) {
+        /* The column walker below needs one layout; copy each column out. */
+        double *col = (double *)malloc((size_t)nk * 7 * sizeof(double));
+        if (!col) {
+            failed = 1;
+            continue;
+        }
+        double *ca = col, *cb = col + nk, *cc = col + 2 * nk, *cd = col + 3 * nk, *cx = col + 4 * nk,
+               *cp = col + 5 * nk, *dp = col + 6 * nk;
         for (int i = -e; i < ni + e; ++i) {
             for (int k = 0; k < nk; ++k) {
                 ca[k] = a[idx(ni, nj, ha, i, j, k)];
@@ -251,8 +267,9 @@ int oracle_thomas(int ni, int nj, int nk, const double *a, int ha, const double 
             thomas_column(nk, ca, cb, cc, cd, 1, cx, cp, dp);
             for (int k = 0; k < nk; ++k) x[idx(ni, nj, hx, i, j, k)] = cx[k];
         }
-    free(col);
-    return OK;
+        free(col);
+    }
+    return failed ? ERR_MEM : OK;
 }
 
 /* Transposed solve T^T lam = g per column.  T^T has sub-diagonal c(k-1),
@@ -324,6 +341,7 @@ int oracle_vdiff(int ni, int nj, int nk, const double *x, int hx, double kappa, 
                  int e)
 {
     if (bad_dims(ni, nj, nk) || e < 0 || hx < e || hy < e) return ERR_ARG;
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < nk; ++k)
         for (int j = -e; j < nj + e; ++j)
             for (int i = -e; i < ni + e; ++i) {
@@ -373,6 +391,7 @@ int oracle_hgrad(int ni, int nj, int nk, const double *y, int hy, double beta_h,
                  double *z, int hz, int e)
 {
     if (bad_dims(ni, nj, nk) || e < 0 || hy < e + 1 || hz < e) return ERR_ARG;
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < nk; ++k)
         for (int j = -e; j < nj + e; ++j)
             for (int i = -e; i < ni + e; ++i) {

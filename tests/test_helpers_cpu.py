@@ -54,12 +54,29 @@ def test_bench_cpu_leg_times_the_oracle_and_checks_kept_outputs():
                             bench.DT)
     bad = ref.copy()
     bad[1, 2, 3] += 1e-3 * np.abs(ref).max()
-    base, errs = bench.cpu_baseline(ni, nj, nk, {"exact": {"f": f, "x": ref}, "bad": {"f": f, "x": bad}},
-                                    budget_s=0.05)
-    assert base["kind"] == "oracle" and base["unit"] == "Gpoints/s" and base["cores"] == 1
-    assert base["value"] > 0 and "%dx%dx%d" % (ni, nj, nk) in base["sample"]
-    assert errs["exact"] == {"normwise": 0.0, "rms": 0.0}
+    checks = [("exact", "hdiff_vadv", {"f": f, "x": ref}), ("bad", "hdiff_vadv", {"f": f, "x": bad}),
+              ("hd", "hdiff", {"f": f, "x": oracle.hdiff(f["u"], 2, f["coeff"], 2)})]
+    base, errs = bench.cpu_baseline(ni, nj, nk, checks, budget_s=0.05)
+    assert base["kind"] == "oracle" and base["unit"] == "Gpoints/s"
+    assert base["cores"] == oracle.threads() >= 1
+    assert base["value"] > 0 and base["single_thread_value"] > 0
+    assert "%dx%dx%d" % (ni, nj, nk) in base["sample"]
+    assert base["host"]["cpu_count"] == os.cpu_count()
+    assert errs["exact"] == {"normwise": 0.0, "rms": 0.0} and errs["hd"] == {"normwise": 0.0, "rms": 0.0}
     assert abs(errs["bad"]["normwise"] - 1e-3) < 1e-9 and errs["bad"]["rms"] > 0
+
+
+def test_bench_timing_statistics():
+    sys.path.insert(0, ROOT)
+    import bench
+    st = bench.stats([4.0, 1.0, 3.0, 2.0, 5.0])
+    assert st["median_ms"] == 3.0 and st["q1_ms"] == 2.0 and st["q3_ms"] == 4.0 and st["iqr_ms"] == 2.0
+    assert st["mean_ms"] == 3.0 and st["runs"] == 5
+    r = bench.record(1.5, [2.0] * 3, points=4e9, nbytes=8e9)
+    assert r["Gpoints_s"] == 2000.0 and r["algorithmic_GBs"] == 4000.0 and r["frac_hbm_peak"] == 0.5
+    # pooled errors over several outputs
+    e = bench.pooled_errors([(np.array([1.0, 2.0]), np.array([1.0, 2.5])), (np.array([4.0]), np.array([4.0]))])
+    assert abs(e["normwise"] - 0.5 / 4.0) < 1e-15
 
 
 def test_product_path_and_oracle_are_independent():

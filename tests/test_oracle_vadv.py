@@ -266,3 +266,16 @@ def test_timestep_is_the_chain():
     x = oracle.hdiff_vadv(*args, e=1)
     y = oracle.vdiff(x, 1, 0.1, e=1)
     assert np.array_equal(z, oracle.hgrad(y, 1, 0.05, 0.01))
+
+
+def test_openmp_build_is_bitwise_the_serial_one():
+    # The all-core build splits the outermost loops of the forward stages over
+    # threads without changing any element's arithmetic.
+    f = inputs.fields(37, 23, 19, 3, seed=200513074, storage="f64")
+    args = (f["u"], 3, f["coeff"], 3, f["wcon"], 3, f["a"], 3, f["b"], 3, f["c"], 3, 10.0)
+    x1 = oracle.hdiff_vadv(*args)
+    z1 = oracle.timestep(*args, 0.1, 0.05, 0.01)
+    with oracle.parallel():
+        x2 = oracle.hdiff_vadv(*args)
+        z2 = oracle.timestep(*args, 0.1, 0.05, 0.01)
+    assert np.array_equal(x1, x2) and np.array_equal(z1, z2)
