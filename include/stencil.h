@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define STENCIL_ABI_VERSION 1
+#define STENCIL_ABI_VERSION 2
 
 typedef enum {
     STENCIL_F64 = 0,  /* storage and arithmetic in double */
@@ -128,6 +128,8 @@ typedef struct {
                          grids with few columns; FP32 and FP64, nk >= 8),
                          0 the library's choice (four lanes below 65536
                          columns when no other knob is set) */
+    int32_t tile_i;   /* columns per tile row of the pipelined fused kernels:
+                         64, 128 or 256 where compiled (0: 64) */
 } stencil_config_t;
 
 /* Horizontal diffusion, per level k and interior point (i, j):

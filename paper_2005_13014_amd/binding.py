@@ -50,7 +50,7 @@ class FieldDesc(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("unroll", ctypes.c_int32), ("tile_j", ctypes.c_int32),
                 ("prefetch", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("tile_i", ctypes.c_int32)]
 
 
 class Subdomain(ctypes.Structure):
@@ -219,8 +219,8 @@ def _desc(f):
     return ctypes.byref(f.desc())
 
 
-def config(level=0, unroll=0, tile_j=0, prefetch=0, nontemporal=0, schedule=0):
-    return Config(level, unroll, tile_j, prefetch, nontemporal, schedule)
+def config(level=0, unroll=0, tile_j=0, prefetch=0, nontemporal=0, schedule=0, tile_i=0):
+    return Config(level, unroll, tile_j, prefetch, nontemporal, schedule, tile_i)
 
 
 def _cfg(cfg):

@@ -266,7 +266,7 @@ static bool column_variant(int dtype, const ColumnVariant &v) {
 }
 
 // Resolves the fused variant from the knobs; zero knobs take the fastest
-// variant measured at 512 x 512 x 80 (FP32: two rows of 64 columns per half,
+// variant measured at 512 x 512 x 80 (FP32: four rows of 64 columns per half,
 // four levels prefetched, non-temporal streams, pipelined schedule).  A
 // non-zero knob that names no compiled variant is an error, not a silent
 // substitution.
@@ -283,7 +283,9 @@ static int fused_variant(int dtype, const stencil_config_t &cf, const stencil_fi
         return fail(STENCIL_E_ARG, "schedule must be 0 .. 4 (got %d)", cf.schedule);
     // Four lanes per column: asked for, or the library's choice on a small grid
     // when no other knob is set.  It needs nk >= 8.
-    const bool knobs = cf.tile_j || cf.prefetch || cf.nontemporal;
+    if (cf.tile_i != 0 && cf.tile_i != 64 && cf.tile_i != 128 && cf.tile_i != 256)
+        return fail(STENCIL_E_ARG, "tile_i must be 0, 64, 128 or 256 (got %d)", cf.tile_i);
+    const bool knobs = cf.tile_j || cf.prefetch || cf.nontemporal || cf.tile_i;
     const bool small = static_cast<long long>(u->ni) * u->nj < SMALL_GRID_COLUMNS;
     if (cf.schedule == SCHED_FOUR || (cf.schedule == 0 && !knobs && small && u->nk >= 8)) {
         v.tile_j = cf.tile_j ? cf.tile_j : 1;
@@ -299,23 +301,32 @@ static int fused_variant(int dtype, const stencil_config_t &cf, const stencil_fi
                         "four lanes per column need FP32 or FP64 storage, nk >= 8, tile_j 1, prefetch 4 "
                         "(FP64: 2) and non-temporal streams");
     }
-    v.tile_j = cf.tile_j ? cf.tile_j : 2;
+    // FP32: 64 x 4 tiles (one 512-lane workgroup per CU, two u rows loaded per
+    // lane and level) measured fastest; FP64 (registers for one wave per
+    // SIMD at most levels) and bf16: 64 x 2.  An unset tile height takes the
+    // preferred one where the other knobs name a compiled variant, else 2.
+    const int tjs[2] = {cf.tile_j ? cf.tile_j : dtype == STENCIL_F32 ? 4 : 2, 2};
+    const int ntj = cf.tile_j || tjs[0] == 2 ? 1 : 2;
     v.prefetch = cf.prefetch ? cf.prefetch : dtype == STENCIL_F64 ? 2 : 4;
+    v.tile_i = cf.tile_i ? cf.tile_i : 64;
     const bool nts[2] = {true, false};
     const int order[3] = {SCHED_PIPELINED, SCHED_PERSISTENT, SCHED_STAGED};  // library preference
     bool found = false;
-    for (int q = 0; q < 2 && !found; ++q) {
-        v.nt = nts[q];
-        if ((cf.nontemporal > 0 && !v.nt) || (cf.nontemporal < 0 && v.nt)) continue;
-        for (int r = 0; r < 3 && !found; ++r) {
-            v.sched = cf.schedule ? cf.schedule : order[r];
-            found = column_variant(dtype, v);
+    for (int t = 0; t < ntj && !found; ++t) {
+        v.tile_j = tjs[t];
+        for (int q = 0; q < 2 && !found; ++q) {
+            v.nt = nts[q];
+            if ((cf.nontemporal > 0 && !v.nt) || (cf.nontemporal < 0 && v.nt)) continue;
+            for (int r = 0; r < 3 && !found; ++r) {
+                v.sched = cf.schedule ? cf.schedule : order[r];
+                found = column_variant(dtype, v);
+            }
         }
     }
     if (cf.level != STENCIL_LEVEL_ORIGINAL && !found)
         return fail(STENCIL_E_UNSUPPORTED,
-                    "no compiled fused variant tile_j=%d prefetch=%d nontemporal=%d schedule=%d", v.tile_j,
-                    v.prefetch, cf.nontemporal, cf.schedule);
+                    "no compiled fused variant tile_i=%d tile_j=%d prefetch=%d nontemporal=%d schedule=%d",
+                    v.tile_i, v.tile_j, v.prefetch, cf.nontemporal, cf.schedule);
     *out = v;
     return STENCIL_OK;
 }

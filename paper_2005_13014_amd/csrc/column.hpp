@@ -448,15 +448,16 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
 // next tile are requested before the current tile's back-substitution, so
 // their latency hides behind the output stores instead of opening each tile
 // with an idle wait.  A one-shot grid passes stride = ntiles.
-template <class T, int TJ, int PF, int KH, bool NT, bool EXACT, bool CHAIN>
+template <class T, int TJ, int PF, int KH, bool NT, bool EXACT, bool CHAIN, int TI = 64>
 __device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int first, int stride, int ntiles) {
 #pragma clang fp contract(off)
     using S = Storage<T>;
     using C = typename S::C;
     using IO = BufIO<T>;
     constexpr int CP = NT ? 2 : 0;
-    constexpr int TI = 64, PI = TI + 4, PJ = TJ + 4, MR = PJ / TJ, NH = 64 * TJ;
+    constexpr int PI = TI + 4, PJ = TJ + 4, MR = PJ / TJ, NH = TI * TJ;
     static_assert(PJ % TJ == 0, "tile rows must split evenly over the lanes");
+    static_assert(TI % 64 == 0 && 4 * PJ <= 64, "whole waves per tile row; one wave stages the side columns");
     constexpr int TILE = PJ * PI + 64;
     constexpr uint32_t ES = sizeof(T);
     __shared__ C tile[2 * 3 * TILE];
@@ -464,8 +465,8 @@ __device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int first,
 
     const int tid = threadIdx.x;
     const int half = __builtin_amdgcn_readfirstlane(tid >= NH ? 1 : 0);
-    const int l = tid - half * NH, ti = l & 63;
-    const int tj = __builtin_amdgcn_readfirstlane(l >> 6);
+    const int l = tid - half * NH, ti = l % TI;
+    const int tj = __builtin_amdgcn_readfirstlane(l / TI);
     const int I = p.I, J = p.J, K = p.K, sj = p.sj;
     const uint32_t sk_bytes = static_cast<uint32_t>(p.sk) * ES;
 
@@ -480,10 +481,12 @@ __device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int first,
     int lmain[MR];
 #pragma unroll
     for (int m = 0; m < MR; ++m) lmain[m] = (tj + m * TJ) * PI + ti + 2;
-    const bool side_wave = tj == 0;
+    // The side columns c in {0, 1, TI + 2, TI + 3} are staged by the first
+    // 4 PJ lanes of the half's first wave (its other lanes write a dummy slot).
+    const bool side_wave = __builtin_amdgcn_readfirstlane(l >> 6) == 0;
     const int sr = min(l >> 2, PJ - 1), sq = l & 3;
-    const int sc = sq < 2 ? sq : sq + 64;
-    const int lside = l < 4 * PJ ? sr * PI + sc : PJ * PI + ti;
+    const int sc = sq < 2 ? sq : sq + TI;
+    const int lside = l < 4 * PJ ? sr * PI + sc : PJ * PI + (l & 63);
 
     // Per-tile lane offsets (bytes from each field's interior origin).
     uint32_t vmain[MR], vside = 0, vcol = 0;
@@ -642,28 +645,29 @@ __device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int first,
     }
 }
 
-template <class T, int TJ, int PF, int KH, int WPE, bool NT, bool EXACT, bool CHAIN>
-__global__ __launch_bounds__(128 * TJ) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void
+template <class T, int TJ, int PF, int KH, int WPE, bool NT, bool EXACT, bool CHAIN, int TI>
+__global__ __launch_bounds__(2 * TI * TJ) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void
 k_column_pipe(ColumnArgs p, int ntiles) {
     // Consecutive tile positions share an XCD (and its L2) in every round.
-    column_tile_pipe<T, TJ, PF, KH, NT, EXACT, CHAIN>(p, xcd_tile(blockIdx.x, gridDim.x), gridDim.x, ntiles);
+    column_tile_pipe<T, TJ, PF, KH, NT, EXACT, CHAIN, TI>(p, xcd_tile(blockIdx.x, gridDim.x), gridDim.x,
+                                                          ntiles);
 }
 
 // CHAIN: a persistent grid of resident workgroups walks the tiles; otherwise
-// one workgroup per tile.
-template <class T, int TJ, int PF, int KH, int WPE, bool NT, bool EXACT = false, bool CHAIN = false>
+// one workgroup per tile.  Tiles are TI x TJ columns.
+template <class T, int TJ, int PF, int KH, int WPE, bool NT, bool EXACT = false, bool CHAIN = false, int TI = 64>
 static hipError_t launch_column_pipe_t(ColumnArgs a, hipStream_t st) {
     if ((EXACT && a.K != 2 * KH) || (a.K + 1) / 2 > KH) return hipErrorInvalidValue;
-    a.nbi = (a.I + 63) / 64;
+    a.nbi = (a.I + TI - 1) / TI;
     a.nbj = (a.J + TJ - 1) / TJ;
     const int ntiles = a.nbi * a.nbj;
-    auto kern = k_column_pipe<T, TJ, PF, KH, WPE, NT, EXACT, CHAIN>;
+    auto kern = k_column_pipe<T, TJ, PF, KH, WPE, NT, EXACT, CHAIN, TI>;
     int grid = ntiles;
     if (CHAIN) {
-        const int res = resident_workgroups(reinterpret_cast<const void *>(kern), 128 * TJ);
+        const int res = resident_workgroups(reinterpret_cast<const void *>(kern), 2 * TI * TJ);
         if (res > 0 && res < grid) grid = res;
     }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(128 * TJ), 0, st, a, ntiles);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(2 * TI * TJ), 0, st, a, ntiles);
     return hipGetLastError();
 }
 
@@ -736,12 +740,14 @@ struct ColumnEntry {
     bool nt;
     int sched;
     hipError_t (*launch)(const ColumnArgs &, hipStream_t);
+    int tile_i = 64;
 };
 
-template <int N>
-static const ColumnEntry *find_column_entry(const ColumnEntry (&tab)[N], int tj, int pf, bool nt, int sched) {
+template <int N, class Variant>
+static const ColumnEntry *find_column_entry(const ColumnEntry (&tab)[N], const Variant &v) {
     for (int q = 0; q < N; ++q)
-        if (tab[q].tile_j == tj && tab[q].prefetch == pf && tab[q].nt == nt && tab[q].sched == sched)
+        if (tab[q].tile_j == v.tile_j && tab[q].prefetch == v.prefetch && tab[q].nt == v.nt &&
+            tab[q].sched == v.sched && tab[q].tile_i == v.tile_i)
             return &tab[q];
     return nullptr;
 }

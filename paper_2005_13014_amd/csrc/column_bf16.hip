@@ -41,16 +41,17 @@ static const ColumnEntry kFused[] = {
     {2, 4, true, 1, staged<true, 2, 4, true>},
     {2, 4, true, 2, pipelined<2, 4, true, false>},
     {2, 8, true, 2, pipelined<2, 8, true, false>},
+    {4, 4, true, 2, pipelined<4, 4, true, false>},
 };
 
 bool column_variant_bf16(const ColumnVariant &v) {
     if (v.sched == SCHED_FOUR) return false;
-    return find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.sched) != nullptr;
+    return find_column_entry(kFused, v) != nullptr;
 }
 
 hipError_t launch_column_bf16(bool fused, const ColumnArgs &a, const ColumnVariant &v, hipStream_t st) {
     if (!fused) return staged<false, 2, 4, false>(a, st);
-    const ColumnEntry *e = find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.sched);
+    const ColumnEntry *e = find_column_entry(kFused, v);
     return e ? e->launch(a, st) : hipErrorInvalidValue;
 }
 

@@ -55,13 +55,13 @@ static const ColumnEntry kFused[] = {
 
 bool column_variant_f64(const ColumnVariant &v) {
     if (v.sched == SCHED_FOUR) return v.tile_j == 1 && v.prefetch == 2 && v.nt;
-    return find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.sched) != nullptr;
+    return find_column_entry(kFused, v) != nullptr;
 }
 
 hipError_t launch_column_f64(bool fused, const ColumnArgs &a, const ColumnVariant &v, hipStream_t st) {
     if (!fused) return staged<false, 2, 2, false>(a, st);
     if (v.sched == SCHED_FOUR) return four_lanes(a, st);
-    const ColumnEntry *e = find_column_entry(kFused, v.tile_j, v.prefetch, v.nt, v.sched);
+    const ColumnEntry *e = find_column_entry(kFused, v);
     return e ? e->launch(a, st) : hipErrorInvalidValue;
 }
 

@@ -24,7 +24,8 @@ enum { SCHED_STAGED = 1, SCHED_PIPELINED = 2, SCHED_PERSISTENT = 3, SCHED_FOUR =
 struct ColumnVariant {
     int tile_j, prefetch;
     bool nt;
-    int sched;  // SCHED_*
+    int sched;        // SCHED_*
+    int tile_i = 64;  // columns per tile row (pipelined kernels)
 };
 bool column_variant_f64(const ColumnVariant &v);
 bool column_variant_f32(const ColumnVariant &v);

@@ -192,8 +192,23 @@ def test_fused_variants_are_bitwise_identical(tj, pf, nt, sched):
     assert np.array_equal(got.to_numpy(interior=True), base)
 
 
+@pytest.mark.parametrize("ti,tj,pf,sched", [(128, 1, 4, 2), (128, 2, 4, 2), (256, 1, 4, 2), (64, 4, 2, 2)])
+@pytest.mark.parametrize("shape", [(200, 37, 80), (300, 9, 33), (1, 3, 5), (513, 2, 96)])
+def test_wide_tiles_are_bitwise_identical(ti, tj, pf, sched, shape):
+    """Pipelined tiles 128 or 256 columns wide, or four rows tall (ragged
+    last tile in i and j, depths below, at and above the register buckets)
+    give the bits of the staged 64 x 2 tile."""
+    ni, nj, nk = shape
+    f = inputs.fields(ni, nj, nk, 2, seed=SEED + 41, storage="f32")
+    base = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(schedule=1)).to_numpy(interior=True)
+    x = run_hdiff_vadv(f, ni, nj, nk, 2, "f32", cfg=B.config(tile_i=ti, tile_j=tj, prefetch=pf, nontemporal=1,
+                                                                schedule=sched))
+    assert np.array_equal(x.to_numpy(interior=True), base)
+    assert halo_untouched(x)
+
+
 @pytest.mark.parametrize("dtype,tj,pf,nt", [("f64", 2, 2, 1), ("f64", 2, 2, -1), ("bf16", 2, 4, 1),
-                                             ("bf16", 2, 8, 1), ("bf16", 4, 4, -1)])
+                                             ("bf16", 2, 8, 1), ("bf16", 4, 4, -1), ("bf16", 4, 4, 1)])
 @pytest.mark.parametrize("nk", [7, 80])
 def test_other_storage_variants_are_bitwise_identical(dtype, tj, pf, nt, nk):
     """FP64 and bf16 storage: every compiled tile shape, prefetch depth,
