@@ -293,8 +293,10 @@ typedef struct {
 enum {
     STENCIL_PROGRAM_GRAPH = 1,    /* capture the launches in a hipGraph cached on
                                      the program signature and replay it */
-    STENCIL_PROGRAM_AUTOTUNE = 2  /* time the candidate kernel configurations on
+    STENCIL_PROGRAM_AUTOTUNE = 2, /* time the candidate kernel configurations on
                                      first use (synchronises the stream once) */
+    STENCIL_PROGRAM_STAGED = 4    /* only the staged level loop for the column
+                                     stages (same results; for comparisons) */
 };
 
 /* Runs the program.  All fields of one subdomain share dtype, extents and

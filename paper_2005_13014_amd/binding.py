@@ -28,7 +28,7 @@ ELEM_SIZE = {"f64": 8, "f32": 4, "bf16": 2}
 
 LEVEL_DEFAULT, LEVEL_ORIGINAL, LEVEL_INLINE = 0, 1, 2
 STAGE_HDIFF, STAGE_VADV, STAGE_VDIFF, STAGE_HGRAD, STAGE_VDIFF_IMPLICIT = 1, 2, 4, 8, 16
-PROGRAM_GRAPH, PROGRAM_AUTOTUNE = 1, 2
+PROGRAM_GRAPH, PROGRAM_AUTOTUNE, PROGRAM_STAGED = 1, 2, 4
 
 STATUS = {0: "OK", 1: "E_NULL", 2: "E_DTYPE", 3: "E_SHAPE", 4: "E_STRIDE", 5: "E_HALO",
           6: "E_ALIAS", 7: "E_UNSUPPORTED", 8: "E_HIP", 9: "E_ARG"}

@@ -448,13 +448,21 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
 // next tile are requested before the current tile's back-substitution, so
 // their latency hides behind the output stores instead of opening each tile
 // with an idle wait.  A one-shot grid passes stride = ntiles.
-template <class T, int TJ, int PF, int KH, bool NT, bool EXACT, bool CHAIN, int TI = 64>
-__device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int first, int stride, int ntiles) {
+//
+// VD selects the vertical-diffusion epilogue of column_backsub (0: x is the
+// output); NTX makes the output non-temporal on its own (for the batched
+// timestep, whose coefficient fields are shared by several fields and keep
+// the default policy).
+template <class T, int TJ, int PF, int KH, bool NT, bool EXACT, bool CHAIN, int TI = 64, int VD = 0,
+          bool NTX = NT>
+__device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int first, int stride, int ntiles,
+                                                 double kappa = 0.0) {
 #pragma clang fp contract(off)
     using S = Storage<T>;
     using C = typename S::C;
     using IO = BufIO<T>;
     constexpr int CP = NT ? 2 : 0;
+    constexpr int CPX = NTX ? 2 : 0;
     constexpr int PI = TI + 4, PJ = TJ + 4, MR = PJ / TJ, NH = TI * TJ;
     static_assert(PJ % TJ == 0, "tile rows must split evenly over the lanes");
     static_assert(TI % 64 == 0 && 4 * PJ <= 64, "whole waves per tile row; one wave stages the side columns");
@@ -638,8 +646,8 @@ __device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int first,
 #pragma unroll
             for (int q = 0; q < PF && q < KH; ++q) load(q, q);
         }
-        column_backsub<T, 0, KH, CP>(rx, vx, sk_bytes, store, half, K, M, nsteps, shift, level, P, D, x_lo, x_hi,
-                                     0.0, xch, tid, half ? l : NH + l);
+        column_backsub<T, VD, KH, CPX>(rx, vx, sk_bytes, store, half, K, M, nsteps, shift, level, P, D, x_lo,
+                                       x_hi, kappa, xch, tid, half ? l : NH + l);
         if (!more) break;
         t = tn;
     }
@@ -719,6 +727,24 @@ k_column_batch(ColumnBatch b) {
     // L2): default policy; the output streams.  (The software-pipelined tile
     // measured no faster here: the coefficient re-reads hit L2.)
     column_tile<T, true, VD, TJ, PF, KH, false, false, true>(a, tile % a.nbi, tile / a.nbi, b.kappa);
+}
+
+// The same table over the software-pipelined tile (one barrier per level,
+// the FP64 elimination of level s - 2 interleaved with hdiff of level s).
+template <class T, int VD, int TJ, int PF, int KH, int WPE>
+__global__ __launch_bounds__(128 * TJ) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void
+k_column_batch_pipe(ColumnBatch b) {
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    int s = 0;
+    while (s + 1 < b.nsub && b.sub[s + 1].tile0 <= t) ++s;
+    const ColumnBatchSub &sb = b.sub[s];
+    const int local = t - sb.tile0;
+    const int f = local % sb.nfields, tile = local / sb.nfields;
+    ColumnArgs a = sb.a;
+    a.u = sb.u[f];
+    a.x = sb.x[f];
+    column_tile_pipe<T, TJ, PF, KH, false, false, false, 64, VD, true>(a, tile, a.nbi * a.nbj, a.nbi * a.nbj,
+                                                                      b.kappa);
 }
 
 // ---------------------------------------------------------------------------

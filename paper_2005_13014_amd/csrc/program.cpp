@@ -10,9 +10,9 @@
 //     BATCH_FIELDS fields (the table rides in the kernel arguments);
 //   - with hgrad, y goes to library-owned scratch and a batched 7-point
 //     kernel writes z.
-// With STENCIL_PROGRAM_AUTOTUNE the compiled (tile_j, prefetch) variants of
-// the column kernel are timed once per program signature and the fastest is
-// kept.  With STENCIL_PROGRAM_GRAPH the launches are captured once per
+// With STENCIL_PROGRAM_AUTOTUNE the compiled (tile_j, prefetch, level-loop
+// schedule) variants of the column kernel are timed once per program
+// signature and the fastest is kept; otherwise the preferred one runs.  With STENCIL_PROGRAM_GRAPH the launches are captured once per
 // signature into a hipGraph that later calls replay.
 #include <hip/hip_runtime.h>
 
@@ -42,15 +42,15 @@ int check_halo(const stencil_field_t *f, const char *name, int need);
 size_t elem_size(int dtype);
 bool empty(const stencil_field_t *f);
 
-hipError_t launch_column_batch_f64(const ColumnBatch &, int, int, int, int, int, hipStream_t);
-hipError_t launch_column_batch_f32(const ColumnBatch &, int, int, int, int, int, hipStream_t);
-hipError_t launch_column_batch_bf16(const ColumnBatch &, int, int, int, int, int, hipStream_t);
+hipError_t launch_column_batch_f64(const ColumnBatch &, int, int, int, int, int, int, int, hipStream_t);
+hipError_t launch_column_batch_f32(const ColumnBatch &, int, int, int, int, int, int, int, hipStream_t);
+hipError_t launch_column_batch_bf16(const ColumnBatch &, int, int, int, int, int, int, int, hipStream_t);
 hipError_t launch_hgrad_batch_f64(const HgradBatch &, int, hipStream_t);
 hipError_t launch_hgrad_batch_f32(const HgradBatch &, int, hipStream_t);
 hipError_t launch_hgrad_batch_bf16(const HgradBatch &, int, hipStream_t);
-bool batch_variant_f64(int, int);
-bool batch_variant_f32(int, int);
-bool batch_variant_bf16(int, int);
+bool batch_variant_f64(int, int, int, int);
+bool batch_variant_f32(int, int, int, int);
+bool batch_variant_bf16(int, int, int, int);
 
 #define TRY(x)                             \
     do {                                   \
@@ -60,17 +60,23 @@ bool batch_variant_bf16(int, int);
 
 namespace {
 
+// A column-kernel variant: rows per tile, levels prefetched, level loop
+// (1 staged, 2 software-pipelined), fields of one tile per workgroup (the
+// compiled kernels take one; the planner counts tiles with it).
 struct Variant {
-    int tj, pf;
+    int tj, pf, sched, fpw;
 };
 
-std::vector<Variant> variants_for(int dtype) {
+// Compiled variants, the library's preference first (the choice without
+// autotuning); staged_only keeps the staged level loop alone.
+std::vector<Variant> variants_for(int dtype, bool staged_only) {
     std::vector<Variant> v;
-    const Variant all[] = {{2, 4}, {4, 4}, {2, 2}};
+    const Variant all[] = {{2, 4, 2, 1}, {2, 4, 1, 1}, {4, 4, 2, 1}, {4, 4, 1, 1}, {2, 2, 1, 1}};
     for (const Variant &c : all) {
-        const bool ok = dtype == STENCIL_F64   ? batch_variant_f64(c.tj, c.pf)
-                        : dtype == STENCIL_F32 ? batch_variant_f32(c.tj, c.pf)
-                                               : batch_variant_bf16(c.tj, c.pf);
+        if (staged_only && c.sched != 1) continue;
+        const bool ok = dtype == STENCIL_F64   ? batch_variant_f64(c.tj, c.pf, c.sched, c.fpw)
+                        : dtype == STENCIL_F32 ? batch_variant_f32(c.tj, c.pf, c.sched, c.fpw)
+                                               : batch_variant_bf16(c.tj, c.pf, c.sched, c.fpw);
         if (ok) v.push_back(c);
     }
     return v;
@@ -116,7 +122,7 @@ struct Entry {
     hipStream_t st = nullptr;
     Plan plan;
     Buffer *buf = nullptr;
-    Variant var{0, 0};
+    Variant var{0, 0, 0, 1};
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
 };
@@ -218,7 +224,7 @@ int check_program(const stencil_program_t *prog, int *dtype_out) {
     const int chain3 = chain2 | STENCIL_STAGE_HGRAD, chain3i = chain2i | STENCIL_STAGE_HGRAD;
     if (st != chain1 && st != chain2 && st != chain3 && st != chain2i && st != chain3i)
         return fail(STENCIL_E_ARG, "stages must be HDIFF|VADV[|VDIFF or VDIFF_IMPLICIT[|HGRAD]] (got %d)", st);
-    if (prog->flags & ~(STENCIL_PROGRAM_GRAPH | STENCIL_PROGRAM_AUTOTUNE))
+    if (prog->flags & ~(STENCIL_PROGRAM_GRAPH | STENCIL_PROGRAM_AUTOTUNE | STENCIL_PROGRAM_STAGED))
         return fail(STENCIL_E_ARG, "unknown program flags %d", prog->flags);
     if (!std::isfinite(prog->dt) || !std::isfinite(prog->kappa) || !std::isfinite(prog->beta_h) ||
         !std::isfinite(prog->beta_v))
@@ -304,9 +310,10 @@ ColumnArgs column_args_ext(const stencil_field_t &cf, const stencil_subdomain_t 
     return a;
 }
 
-// Builds the launch tables for a given column-kernel tile height.  Scratch
-// offsets for y are laid out when `scratch` is null (sizing pass).
-int build_plan(const stencil_program_t *prog, int dtype, int tj, char *scratch, Plan *plan) {
+// Builds the launch tables for a given column-kernel tile height and number
+// of fields per workgroup.  Scratch offsets for y are laid out when
+// `scratch` is null (sizing pass).
+int build_plan(const stencil_program_t *prog, int dtype, int tj, int fpw, char *scratch, Plan *plan) {
     plan->dtype = dtype;
     plan->vdiff = (prog->stages & STENCIL_STAGE_VDIFF_IMPLICIT) ? 2 : (prog->stages & STENCIL_STAGE_VDIFF) ? 1 : 0;
     plan->hgrad = (prog->stages & STENCIL_STAGE_HGRAD) != 0;
@@ -363,7 +370,7 @@ int build_plan(const stencil_program_t *prog, int dtype, int tj, char *scratch, 
                     void *out = plan->hgrad ? static_cast<void *>(ys[s][f0 + f]) : sd.z[f0 + f].origin;
                     sb.x[f] = out ? static_cast<char *>(out) - shift : nullptr;
                 }
-                tiles += a.nbi * a.nbj * sb.nfields;
+                tiles += a.nbi * a.nbj * ((sb.nfields + fpw - 1) / fpw);
             }
         }
         flush();
@@ -412,9 +419,15 @@ hipError_t enqueue(const Plan &plan, Variant v, hipStream_t st, bool columns_onl
     for (const ColumnLaunch &cl : plan.col) {
         hipError_t e;
         switch (plan.dtype) {
-        case STENCIL_F64: e = launch_column_batch_f64(cl.b, plan.vdiff, cl.kh, v.tj, v.pf, cl.ntiles, st); break;
-        case STENCIL_F32: e = launch_column_batch_f32(cl.b, plan.vdiff, cl.kh, v.tj, v.pf, cl.ntiles, st); break;
-        default: e = launch_column_batch_bf16(cl.b, plan.vdiff, cl.kh, v.tj, v.pf, cl.ntiles, st); break;
+        case STENCIL_F64:
+            e = launch_column_batch_f64(cl.b, plan.vdiff, cl.kh, v.tj, v.pf, v.sched, v.fpw, cl.ntiles, st);
+            break;
+        case STENCIL_F32:
+            e = launch_column_batch_f32(cl.b, plan.vdiff, cl.kh, v.tj, v.pf, v.sched, v.fpw, cl.ntiles, st);
+            break;
+        default:
+            e = launch_column_batch_bf16(cl.b, plan.vdiff, cl.kh, v.tj, v.pf, v.sched, v.fpw, cl.ntiles, st);
+            break;
         }
         if (e != hipSuccess) return e;
     }
@@ -435,7 +448,7 @@ hipError_t enqueue(const Plan &plan, Variant v, hipStream_t st, bool columns_onl
 // launch each, five rounds that time every candidate once (interleaved, so
 // that clock and cache drift hit all of them alike); the median decides.
 int autotune(const stencil_program_t *prog, int dtype, char *scratch, hipStream_t st, Variant *best) {
-    const std::vector<Variant> cands = variants_for(dtype);
+    const std::vector<Variant> cands = variants_for(dtype, (prog->flags & STENCIL_PROGRAM_STAGED) != 0);
     constexpr int ROUNDS = 5;
     *best = cands.front();
     hipEvent_t e0, e1;
@@ -450,7 +463,7 @@ int autotune(const stencil_program_t *prog, int dtype, char *scratch, hipStream_
     std::vector<std::vector<float>> ms(cands.size());
     hipError_t e = hipSuccess;
     for (size_t c = 0; c < cands.size() && e == hipSuccess; ++c) {
-        build_plan(prog, dtype, cands[c].tj, scratch, &plans[c]);
+        build_plan(prog, dtype, cands[c].tj, cands[c].fpw, scratch, &plans[c]);
         e = enqueue(plans[c], cands[c], st, true);
     }
     for (int r = 0; r < ROUNDS && e == hipSuccess; ++r)
@@ -546,7 +559,7 @@ STENCIL_API int stencil_program_run(const stencil_program_t *prog, void *stream)
         en->dev = dev;
         en->st = st;
         Plan sizing;
-        build_plan(prog, dtype, 2, nullptr, &sizing);
+        build_plan(prog, dtype, 2, 1, nullptr, &sizing);
         // Make room first, so that an evicted entry's scratch can be reused.
         while (g_lru.size() >= PROGRAM_CACHE_MAX) {
             entry_release(*g_lru.back());
@@ -554,7 +567,7 @@ STENCIL_API int stencil_program_run(const stencil_program_t *prog, void *stream)
         }
         TRY(buffer_get(dev, st, sizing.scratch_bytes, &en->buf));
         char *scratch = en->buf ? static_cast<char *>(en->buf->p) : nullptr;
-        const std::vector<Variant> cands = variants_for(dtype);
+        const std::vector<Variant> cands = variants_for(dtype, (prog->flags & STENCIL_PROGRAM_STAGED) != 0);
         en->var = cands.front();
         if (tune && cands.size() > 1) {
             const int rc = autotune(prog, dtype, scratch, st, &en->var);
@@ -563,7 +576,7 @@ STENCIL_API int stencil_program_run(const stencil_program_t *prog, void *stream)
                 return rc;
             }
         }
-        build_plan(prog, dtype, en->var.tj, scratch, &en->plan);
+        build_plan(prog, dtype, en->var.tj, en->var.fpw, scratch, &en->plan);
         g_lru.push_front(std::move(en));
     }
     Entry &en = *g_lru.front();

@@ -15,13 +15,15 @@ static hipError_t by_levels(const ColumnBatch &b, int kh, int ntiles, hipStream_
     return hipErrorInvalidValue;
 }
 
-bool batch_variant_bf16(int tile_j, int prefetch) {
+bool batch_variant_bf16(int tile_j, int prefetch, int sched, int fpw) {
+    if (sched != 1 || fpw != 1) return false;  // staged, one field per workgroup
     if (tile_j == 2 && prefetch == 4) return true;
     return false;
 }
 
 hipError_t launch_column_batch_bf16(const ColumnBatch &b, int vd, int kh, int tile_j,
-                                   int prefetch, int ntiles, hipStream_t st) {
+                                   int prefetch, int sched, int fpw, int ntiles, hipStream_t st) {
+    if (sched != 1 || fpw != 1) return hipErrorInvalidValue;
     if (tile_j == 2 && prefetch == 4)
         return vd == 2   ? by_levels<2, 2, 4>(b, kh, ntiles, st)
                : vd == 1 ? by_levels<1, 2, 4>(b, kh, ntiles, st)

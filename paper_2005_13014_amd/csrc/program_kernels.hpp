@@ -122,10 +122,15 @@ __global__ __launch_bounds__(64 * TR) void k_hgrad_batch(HgradBatch b) {
     }
 }
 
-template <class T, int VD, int TJ, int PF, int KH, int WPE>
+// PIPE: the software-pipelined tile, else the staged one.
+template <class T, int VD, int TJ, int PF, int KH, int WPE, bool PIPE = false>
 static hipError_t launch_column_batch_t(const ColumnBatch &b, int ntiles, hipStream_t st) {
-    hipLaunchKernelGGL((k_column_batch<T, VD, TJ, PF, KH, WPE>), dim3(ntiles), dim3(128 * TJ), 0, st,
-                       b);
+    if constexpr (PIPE)
+        hipLaunchKernelGGL((k_column_batch_pipe<T, VD, TJ, PF, KH, WPE>), dim3(ntiles), dim3(128 * TJ), 0, st,
+                           b);
+    else
+        hipLaunchKernelGGL((k_column_batch<T, VD, TJ, PF, KH, WPE>), dim3(ntiles), dim3(128 * TJ), 0, st,
+                           b);
     return hipGetLastError();
 }
 

@@ -332,10 +332,10 @@ def test_program_validation():
     p.dt = float("nan")
     assert run_program(p) == 9
     p, keep = program()
-    p.flags = 4                                      # unknown flag
+    p.flags = 8                                      # unknown flag
     assert run_program(p) == 9
     p, keep = program(halo_u=2)
-    p.flags = 1 | 2                                  # known flags pass, the halo check still runs
+    p.flags = 1 | 2 | 4                              # known flags pass, the halo check still runs
     assert run_program(p) == 5
     p, keep = program(nsub=0)
     assert run_program(p) == 0                       # an empty program is a no-op

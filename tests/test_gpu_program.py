@@ -144,6 +144,28 @@ def test_autotune_does_not_change_results():
             assert np.array_equal(z.to_numpy(), rr)
 
 
+@pytest.mark.parametrize("stages", [B.STAGE_HDIFF | B.STAGE_VADV, B.STAGE_HDIFF | B.STAGE_VADV | B.STAGE_VDIFF,
+                                    FULL, FULL_IMPLICIT])
+def test_pipelined_and_staged_column_stages_agree(stages):
+    """The column stages with the software-pipelined level loop (the default)
+    and with the staged one (STENCIL_PROGRAM_STAGED) give the same bits, in
+    every register bucket (1 .. 90 levels, ragged tiles)."""
+    shapes = ((70, 13, 9), (40, 33, 17), (5, 3, 1), (64, 8, 40), (40, 9, 70), (20, 5, 90), (130, 7, 84))
+    data = small_data("f32", nfields=3, shapes=shapes)
+    subs = device_program(data, "f32")
+    run(subs, stages)
+    pipe = [[z.to_numpy() for z in s["z"]] for s in subs]
+    run(subs, stages, flags=B.PROGRAM_STAGED)
+    for s, r in zip(subs, pipe):
+        for z, rr in zip(s["z"], r):
+            assert np.array_equal(z.to_numpy(), rr)
+    worst = 0.0
+    for d, s in zip(data, subs):
+        for f in range(len(d["u"])):
+            worst = max(worst, normwise(s["z"][f].to_numpy(interior=True), reference(d, f, stages)))
+    assert worst <= TOL["f32"]
+
+
 def test_tables_split_over_many_subdomains_and_fields():
     # 10 subdomains (more than one table) and 11 fields (more than one entry).
     shapes = tuple((17 + 3 * q, 6 + q, 5 + q) for q in range(10))
