@@ -341,6 +341,11 @@ def variant_adjoint(n=256, nk=80):
         # gcoeff, gwcon out
         ab = ES[dtype] * (2 * u_cells(n, n, nk) + 8 * n * n * nk)
         out[dtype] = record(w, ms, n * n * nk, ab)
+        lds = B.config(schedule=1)   # the hdiff adjoint on LDS-staged tiles, for comparison
+        w2, ms2 = time_calls(lambda _: B.stencil_hdiff_vadv_adjoint(
+            g["u"], g["coeff"], g["wcon"], g["a"], g["b"], g["c"], DT, g["w"], *gs, cfg=lds), [None], RUNS, WARM)
+        out[dtype]["lds_tiles_median_ms"] = stats(ms2)["median_ms"]
+        fn(None)
         checks.append((dtype, "adjoint", {
             "f": f, "gu": to_host(gs[0], interior=False), "gcoeff": to_host(gs[1]), "gwcon": to_host(gs[2])}))
     return out, checks

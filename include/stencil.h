@@ -194,7 +194,14 @@ int stencil_hdiff_vadv(const stencil_field_t *u, const stencil_field_t *coeff,
  * device scratch: one field-sized plane of the compute type (FP64 storage:
  * two), see the synchronisation rules above.  nk <= 96 and fields below
  * 2 GiB in the compute type (FP32 for bfloat16 storage);
- * STENCIL_E_UNSUPPORTED otherwise. */
+ * STENCIL_E_UNSUPPORTED otherwise.  cfg (may be NULL): schedule 1 evaluates
+ * the hdiff adjoint with LDS-staged tiles, 0 with register strips whose
+ * neighbours in i come from cross-lane shifts (the default; the same
+ * operations, so the same bits); for the strips, tile_j is the rows per
+ * strip and prefetch the levels in flight: 4 or 8 rows with 1 or 2 levels,
+ * or 12 rows with 1 (FP64: 4 rows); 0 takes the default (12 rows and 1
+ * level; FP64 4 and 1); other values STENCIL_E_ARG; the other fields are
+ * ignored. */
 int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stencil_field_t *coeff,
                                const stencil_field_t *wcon, const stencil_field_t *a,
                                const stencil_field_t *b, const stencil_field_t *c, double dt,

@@ -479,6 +479,178 @@ __global__ __launch_bounds__(256) void k_hdiff_adjoint(AdjArgs p, int nbi, int n
 }
 
 // ---------------------------------------------------------------------------
+// hdiff adjoint without LDS: one wave per strip of 64 columns x TJ rows.
+// Lane l holds column x0 + l; the strip's rows live in the lane's registers,
+// so neighbours in j are other registers and neighbours in i are the next or
+// previous lane, fetched with a whole-wave DPP shift.  Each shift leaves the
+// wave's edge lane without a neighbour, and gu at column i depends on columns
+// i - 3 .. i + 3, so a strip writes its middle 58 columns (lanes 3 .. 60) and
+// strips step by 58 columns.  Rows (relative to the strip's first output row
+// y0): u on [-3, TJ+3), g = -coeff gh and lap on [-2, TJ+2), y-faces between
+// rows t and t+1 for t in [-2, TJ+1), x-faces and glap on [-1, TJ+1),
+// outputs on [0, TJ).  The arithmetic is that of the LDS formulation above,
+// operation for operation.  No barriers: the four waves of a workgroup are
+// four neighbouring strips.  Row offsets are wave-uniform (scalar operands of
+// the buffer loads); columns outside a field are clamped onto valid cells
+// and a select applies the zero.
+// ---------------------------------------------------------------------------
+constexpr int ADJ_STRIP = 58;  // output columns per 64-lane strip
+
+// Value of lane l + 1 (from_right) or l - 1 (from_left) of the wave.  A
+// cross-lane read is only meaningful while every lane of the wave is active:
+// a lane disabled in EXEC supplies no value.  So every shift is evaluated in
+// the kernel's uniform control flow, never inside an operand of ?: (which
+// C++ evaluates conditionally, so that the compiler branches around it), and
+// the empty asm keeps the compiler from sinking a shift into the branch of a
+// conditional store that uses it.
+__device__ __forceinline__ int lane_shift(int v, int ctrl) {
+    int r = ctrl == 0x130 ? __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false)
+                          : __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+    asm volatile("" : "+v"(r));
+    return r;
+}
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(lane_shift(__float_as_int(v), 0x130)); }
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(lane_shift(__float_as_int(v), 0x138)); }
+__device__ __forceinline__ double shift_d(double v, int ctrl) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(lane_shift(static_cast<int>(b), ctrl));
+    const uint32_t hi = static_cast<uint32_t>(lane_shift(static_cast<int>(b >> 32), ctrl));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+__device__ __forceinline__ double from_right(double v) { return shift_d(v, 0x130); }
+__device__ __forceinline__ double from_left(double v) { return shift_d(v, 0x138); }
+
+template <class T, int TJ, int PF>
+__global__ __launch_bounds__(256) void k_hdiff_adjoint_dpp(AdjArgs p, int nbi, int nstrips, int kc) {
+#pragma clang fp contract(off)
+    using S = Storage<T>;
+    using C = typename S::C;
+    using IO = BufIO<T>;
+    using IOC = BufIO<C>;
+    using R = typename IO::R;
+    using RC = typename IOC::R;
+    constexpr int NU = TJ + 6, NG = TJ + 4;
+    constexpr uint32_t ES = sizeof(T), ESC = sizeof(C);
+    T *__restrict__ gu = static_cast<T *>(p.gu);
+    T *__restrict__ gcoeff = static_cast<T *>(p.gcoeff);
+    const int I = p.I, J = p.J, K = p.K, sj = p.sj;
+    // Workgroups numbered chunk-major (a chunk is a run of kc levels);
+    // consecutive positions hold neighbouring strips and stay on one XCD.
+    const int ngroups = (nstrips + 3) / 4;
+    const int pos = xcd_tile(blockIdx.x, gridDim.x);
+    const int group = pos % ngroups, chunk = pos / ngroups;
+    const int strip = group * 4 + __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    if (strip >= nstrips) return;
+    const int k0 = chunk * kc, k1 = min(K, k0 + kc);
+    const int bi = strip % nbi, bj = strip / nbi;
+    const int x0 = -5 + ADJ_STRIP * bi, y0 = -2 + TJ * bj;
+    const int lane = threadIdx.x & 63, i = x0 + lane;
+    const bool okcu = i >= -2 && i < I + 2, okcg = i >= 0 && i < I;
+    const bool out_col = lane >= 3 && lane < 3 + ADJ_STRIP && i < I + 2;
+
+    // u from its cell (-2, -2, 0); coeff and gh from the interior origin.
+    const long long cells = static_cast<long long>(K - 1) * p.sk;
+    const auto ru = make_rsrc(static_cast<const T *>(p.u) - 2 - 2 * sj,
+                              static_cast<uint32_t>(((I + 3) + (J + 3) * static_cast<long long>(sj) + cells + 1) * ES));
+    const uint32_t col = static_cast<uint32_t>((I - 1) + (J - 1) * static_cast<long long>(sj) + cells + 1);
+    const auto rcf = make_rsrc(p.coeff, col * ES);
+    const auto rgh = make_rsrc(p.gh, col * ESC);
+    const uint32_t vu = static_cast<uint32_t>(min(max(i, -2), I + 1) + 2);
+    const uint32_t vg = static_cast<uint32_t>(min(max(i, 0), I - 1));
+    auto urow = [&](int t) {  // u row y0 - 3 + t, in elements from u's cell (-2, -2)
+        return static_cast<uint32_t>((min(max(y0 - 3 + t, -2), J + 1) + 2) * sj);
+    };
+    auto grow = [&](int t) {  // g row y0 - 2 + t, from the interior origin
+        return static_cast<uint32_t>(min(max(y0 - 2 + t, 0), J - 1) * sj);
+    };
+
+    R rum[PF][NU], rcv[PF][NG];
+    RC rgv[PF][NG];
+    auto load = [&](int q, int k) {
+        const uint32_t ko = static_cast<uint32_t>(k) * static_cast<uint32_t>(p.sk);
+#pragma unroll
+        for (int t = 0; t < NU; ++t) rum[q][t] = IO::load_raw(ru, vu * ES, (urow(t) + ko) * ES);
+#pragma unroll
+        for (int t = 0; t < NG; ++t) {
+            rcv[q][t] = IO::load_raw(rcf, vg * ES, (grow(t) + ko) * ES);
+            rgv[q][t] = IOC::load_raw(rgh, vg * ESC, (grow(t) + ko) * ESC);
+        }
+    };
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+        if (k0 + q < k1) load(q, k0 + q);
+
+    for (int kk = k0; kk < k1; kk += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = kk + q;
+            if (k >= k1) break;
+            C u[NU], g[NG], gho[TJ];
+#pragma unroll
+            for (int t = 0; t < NU; ++t) {
+                const int j = y0 - 3 + t;
+                u[t] = okcu && j >= -2 && j < J + 2 ? IO::cvt(rum[q][t]) : C(0);
+            }
+#pragma unroll
+            for (int t = 0; t < NG; ++t) {
+                const int j = y0 - 2 + t;
+                const bool ok = okcg && j >= 0 && j < J;
+                const C ghx = IOC::cvt(rgv[q][t]);
+                g[t] = ok ? -IO::cvt(rcv[q][t]) * ghx : C(0);
+                if (t >= 2 && t < TJ + 2) gho[t - 2] = ok ? ghx : C(0);
+            }
+            if (k + PF < k1) load(q, k + PF);
+            // One pass down the strip's rows: at g row t the Laplacian of row
+            // t, the y-face between rows t - 1 and t, the x-face and glap of
+            // row t - 1 and the outputs of row t - 2, so that every value
+            // dies a few rows after it is made.
+            C lap[NG], ue[NG], fy[NG - 1], gfy[NG - 1], fx[NG], glap[NG];
+            const long long ko = static_cast<long long>(k) * p.sk;
+#pragma unroll
+            for (int t = 0; t < NG + 1; ++t) {
+                if (t < NG) {  // Laplacian on g row t (u row t + 1), and u of the next column
+                    const C uc = u[t + 1];
+                    ue[t] = from_right(uc);
+                    const C uw = from_left(uc);
+                    lap[t] = C(4) * uc - ue[t] - uw - u[t + 2] - u[t];
+                }
+                if (t >= 1 && t < NG) {  // y-face between g rows t - 1 and t
+                    const C f = lap[t] - lap[t - 1];
+                    const C du = u[t + 1] - u[t];
+                    const bool kept = !(f * du > C(0));
+                    fy[t - 1] = kept ? f : C(0);
+                    gfy[t - 1] = kept ? g[t - 1] - g[t] : C(0);
+                }
+                const int r = t - 1;  // x-face (between this column and the next) and glap of row r
+                if (r >= 1 && r < NG - 1) {
+                    // (every shift outside the selects: an operand of ?: is evaluated conditionally)
+                    const C lap_e = from_right(lap[r]), g_e = from_right(g[r]);
+                    const C f = lap_e - lap[r];
+                    const C du = ue[r] - u[r + 1];
+                    const bool kept = !(f * du > C(0));
+                    fx[r] = kept ? f : C(0);
+                    const C gfx = kept ? g[r] - g_e : C(0);
+                    glap[r] = from_left(gfx) - gfx + gfy[r - 1] - gfy[r];
+                }
+                const int o = t - 2;  // outputs of row o
+                if (o >= 2 && o < TJ + 2) {
+                    const int j = y0 + o - 2;
+                    const C sv = glap[o];
+                    const C ghv = gho[o - 2];
+                    const C gv = ghv - glap[o - 1] - from_left(sv) + C(4) * sv - from_right(sv) - glap[o + 1];
+                    const C div = fx[o] - from_left(fx[o]) + fy[o] - fy[o - 1];
+                    if (out_col && j < J + 2) {
+                        const long long off = i + static_cast<long long>(j) * sj + ko;
+                        S::store(gu + off, gv);
+                        if (okcg && j >= 0 && j < J) S::store(gcoeff + off, -ghv * div);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 
 // Scratch: gh, and for FP64 storage also h (FP32 and bfloat16 storage
 // evaluate h inside the column kernel); each plane in the compute type with
@@ -491,7 +663,9 @@ size_t adjoint_scratch_bytes(int dtype, int sk, int K) {
 
 template <class T, int KH, bool FUSEH>
 static void launch_vadv_adjoint_t(const AdjArgs &a, hipStream_t st) {
-    constexpr int TJ = 2, PF = 4;
+    // 64 x 2 tiles (64 x 4 and 64 x 1 measured no faster); the outward walk
+    // prefetches 2 levels with h evaluated in-kernel (4 and 8 slower), else 4.
+    constexpr int TJ = 2, PF = FUSEH ? 2 : 4;
     const int nbi = (a.I + 63) / 64, nbj = (a.J + TJ - 1) / TJ;
     if (a.ga || a.gb || a.gc)
         hipLaunchKernelGGL((k_vadv_adjoint<T, TJ, PF, KH, true, FUSEH>), dim3(nbi * nbj), dim3(128 * TJ), 0, st,
@@ -501,8 +675,23 @@ static void launch_vadv_adjoint_t(const AdjArgs &a, hipStream_t st) {
                            st, a, nbi);
 }
 
+template <class T, int TJ, int PF>
+static hipError_t launch_hdiff_adjoint_dpp(const AdjArgs &a, hipStream_t st) {
+    const int nbi = (a.I + 4 + ADJ_STRIP - 1) / ADJ_STRIP, nbj = (a.J + 4 + TJ - 1) / TJ;
+    const long long nstrips = static_cast<long long>(nbi) * nbj, groups = (nstrips + 3) / 4;
+    auto kern = k_hdiff_adjoint_dpp<T, TJ, PF>;
+    const long long slots = resident_workgroups(reinterpret_cast<const void *>(kern), 256);
+    const int kc = level_run(groups, slots, a.K, 1, 1, PF);
+    const long long blocks = groups * ((a.K + kc - 1) / kc);
+    if (blocks > 2147483647LL || nstrips > 2147483647LL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a, nbi,
+                       static_cast<int>(nstrips), kc);
+    return hipGetLastError();
+}
+
 template <class T>
-static hipError_t adjoint_run(AdjArgs a, void *scratch, hipStream_t st) {
+static hipError_t adjoint_run(AdjArgs a, void *scratch, bool staged_hdiff, int strip_rows, int strip_prefetch,
+                              hipStream_t st) {
     using C = typename Storage<T>::C;
     const size_t plane = (static_cast<size_t>(a.sk) * a.K * sizeof(C) + 255) / 256 * 256;
     // FP32 and bfloat16 storage evaluate h inside the column kernel (FUSEH,
@@ -528,8 +717,23 @@ static hipError_t adjoint_run(AdjArgs a, void *scratch, hipStream_t st) {
     else launch_vadv_adjoint_t<T, 48, FUSEH>(a, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // Rows per hdiff-adjoint tile: 8 (two per thread) where the staged tile
-    // fits often enough in LDS; FP64's twice larger tile keeps 4.  Each
+    if (!staged_hdiff) {
+        // Register strips, DPP neighbours: rows per strip and levels in flight
+        // from the caller's knobs, else 12 rows and one level (measured at
+        // 256 x 256 x 80 FP32: reverse pass 0.0704 ms against 0.0722 for 8
+        // rows and two levels, 0.0747 for 8 and one, 0.0754 for 16 and one);
+        // FP64 4 rows and one level (its values take twice the registers).
+        const bool f64 = std::is_same<T, double>::value;
+        const int tj = strip_rows ? strip_rows : f64 ? 4 : 12, pf = strip_prefetch ? strip_prefetch : 1;
+        if (tj == 4 && pf == 1) return launch_hdiff_adjoint_dpp<T, 4, 1>(a, st);
+        if (tj == 4 && pf == 2) return launch_hdiff_adjoint_dpp<T, 4, 2>(a, st);
+        if (!f64 && tj == 8 && pf == 1) return launch_hdiff_adjoint_dpp<T, 8, 1>(a, st);
+        if (!f64 && tj == 8 && pf == 2) return launch_hdiff_adjoint_dpp<T, 8, 2>(a, st);
+        if (!f64 && tj == 12 && pf == 1) return launch_hdiff_adjoint_dpp<T, 12, 1>(a, st);
+        return hipErrorInvalidValue;
+    }
+    // The LDS formulation: rows per tile 8 (two per thread) where the staged
+    // tile fits often enough in LDS; FP64's twice larger tile keeps 4.  Each
     // workgroup marches over kc levels with HPF levels in flight; kc is chosen
     // against the resident workgroup count (a mostly empty last round of
     // workgroups costs nearly as much as a full one).
@@ -582,6 +786,8 @@ hipError_t adjoint_fixed_scratch(void **out) {
 }
 
 hipError_t launch_adjoint(int dtype, const AdjointArgs &x, void *scratch, hipStream_t st) {
+    const bool staged = x.hdiff_schedule == 1;
+    const int rows = x.hdiff_tile_j, pf = x.hdiff_prefetch;
     AdjArgs a{};
     a.u = x.u; a.coeff = x.coeff; a.wcon = x.wcon; a.a = x.a; a.b = x.b; a.c = x.c; a.w = x.w;
     a.gu = x.gu; a.gcoeff = x.gcoeff; a.gwcon = x.gwcon;
@@ -589,9 +795,9 @@ hipError_t launch_adjoint(int dtype, const AdjointArgs &x, void *scratch, hipStr
     a.I = x.I; a.J = x.J; a.K = x.K; a.sj = x.sj; a.sk = x.sk;
     a.dt = x.dt;
     switch (dtype) {
-    case DT_F64: return adjoint_run<double>(a, scratch, st);
-    case DT_F32: return adjoint_run<float>(a, scratch, st);
-    case DT_BF16: return adjoint_run<uint16_t>(a, scratch, st);
+    case DT_F64: return adjoint_run<double>(a, scratch, staged, rows, pf, st);
+    case DT_F32: return adjoint_run<float>(a, scratch, staged, rows, pf, st);
+    case DT_BF16: return adjoint_run<uint16_t>(a, scratch, staged, rows, pf, st);
     }
     return hipErrorInvalidValue;
 }

@@ -522,7 +522,8 @@ int adjoint_entry(const stencil_field_t *u, const stencil_field_t *coeff, const 
                   const stencil_field_t *a, const stencil_field_t *b, const stencil_field_t *c, double dt,
                   const stencil_field_t *w, const stencil_field_t *gu, const stencil_field_t *gcoeff,
                   const stencil_field_t *gwcon, const stencil_field_t *xf, const stencil_field_t *ga,
-                  const stencil_field_t *gb, const stencil_field_t *gc, void *stream, bool fixed) {
+                  const stencil_field_t *gb, const stencil_field_t *gc, const stencil_config_t *cfg,
+                  void *stream, bool fixed) {
     // Inputs first, outputs last (the alias check takes the last nout as outputs).
     const stencil_field_t *fs[15];
     const char *names[15];
@@ -543,6 +544,16 @@ int adjoint_entry(const stencil_field_t *u, const stencil_field_t *coeff, const 
     TRY(check_halo(u, "u", 2));
     TRY(check_halo(gu, "gu", 2));
     TRY(check_dt(dt));
+    if (cfg && cfg->schedule != 0 && cfg->schedule != 1)
+        return fail(STENCIL_E_ARG, "adjoint schedule must be 0 (register strips) or 1 (LDS tiles), got %d",
+                    cfg->schedule);
+    if (cfg && ((cfg->tile_j != 0 && cfg->tile_j != 4 && cfg->tile_j != 8 && cfg->tile_j != 12) ||
+                (cfg->tile_j > 4 && u->dtype == STENCIL_F64) || cfg->prefetch < 0 || cfg->prefetch > 2 ||
+                (cfg->tile_j == 12 && cfg->prefetch == 2)))
+        return fail(STENCIL_E_ARG,
+                    "adjoint register strips take tile_j 4 or 8 with prefetch 1 or 2, or tile_j 12 with prefetch "
+                    "1 (FP64: tile_j 4) (got %d, %d)",
+                    cfg->tile_j, cfg->prefetch);
     if (empty(u)) return STENCIL_OK;
     if (u->nk > KMAX_ADJOINT)
         return fail(STENCIL_E_UNSUPPORTED, "adjoint supports nk <= %d", KMAX_ADJOINT);
@@ -565,6 +576,9 @@ int adjoint_entry(const stencil_field_t *u, const stencil_field_t *coeff, const 
     x.I = u->ni; x.J = u->nj; x.K = u->nk;
     x.sj = static_cast<int>(u->sj); x.sk = static_cast<int>(u->sk);
     x.dt = dt;
+    x.hdiff_schedule = cfg ? cfg->schedule : 0;
+    x.hdiff_tile_j = cfg ? cfg->tile_j : 0;
+    x.hdiff_prefetch = cfg ? cfg->prefetch : 0;
     const size_t need = adjoint_scratch_bytes(u->dtype, x.sk, x.K);
     if (fixed) {
         if (need > ADJOINT_FIXED_SCRATCH_BYTES)
@@ -593,8 +607,7 @@ STENCIL_API int stencil_hdiff_vadv_adjoint(const stencil_field_t *u, const stenc
                                            const stencil_field_t *ga, const stencil_field_t *gb,
                                            const stencil_field_t *gc, const stencil_config_t *cfg,
                                            void *stream) {
-    (void)cfg;
-    return adjoint_entry(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon, xf, ga, gb, gc, stream, false);
+    return adjoint_entry(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon, xf, ga, gb, gc, cfg, stream, false);
 }
 
 STENCIL_API int stencil_hdiff_vadv_adjoint_noalloc(const stencil_field_t *u, const stencil_field_t *coeff,
@@ -606,8 +619,7 @@ STENCIL_API int stencil_hdiff_vadv_adjoint_noalloc(const stencil_field_t *u, con
                                                    const stencil_field_t *ga, const stencil_field_t *gb,
                                                    const stencil_field_t *gc, const stencil_config_t *cfg,
                                                    void *stream) {
-    (void)cfg;
-    return adjoint_entry(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon, xf, ga, gb, gc, stream, true);
+    return adjoint_entry(u, coeff, wcon, a, b, c, dt, w, gu, gcoeff, gwcon, xf, ga, gb, gc, cfg, stream, true);
 }
 
 STENCIL_API int stencil_hdiff_vadv_jvp(const stencil_field_t *u, const stencil_field_t *coeff,

@@ -62,6 +62,9 @@ struct AdjointArgs {
     void *ga, *gb, *gc;    // optional matrix gradients (nullptr skips)
     int I, J, K, sj, sk;
     double dt;
+    int hdiff_schedule;    // hdiff adjoint: 1 the LDS-staged tile, else register strips
+    int hdiff_tile_j;      // register strips: rows per strip (4 or 8; FP64 4), 0 default
+    int hdiff_prefetch;    // register strips: levels in flight (1 or 2), 0 default
 };
 constexpr int KMAX_ADJOINT = 96;
 size_t adjoint_scratch_bytes(int dtype, int sk, int K);
