@@ -496,29 +496,10 @@ __global__ __launch_bounds__(256) void k_hdiff_adjoint(AdjArgs p, int nbi, int n
 // ---------------------------------------------------------------------------
 constexpr int ADJ_STRIP = 58;  // output columns per 64-lane strip
 
-// Value of lane l + 1 (from_right) or l - 1 (from_left) of the wave.  A
-// cross-lane read is only meaningful while every lane of the wave is active:
-// a lane disabled in EXEC supplies no value.  So every shift is evaluated in
-// the kernel's uniform control flow, never inside an operand of ?: (which
-// C++ evaluates conditionally, so that the compiler branches around it), and
-// the empty asm keeps the compiler from sinking a shift into the branch of a
-// conditional store that uses it.
-__device__ __forceinline__ int lane_shift(int v, int ctrl) {
-    int r = ctrl == 0x130 ? __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false)
-                          : __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
-    asm volatile("" : "+v"(r));
-    return r;
-}
-__device__ __forceinline__ float from_right(float v) { return __int_as_float(lane_shift(__float_as_int(v), 0x130)); }
-__device__ __forceinline__ float from_left(float v) { return __int_as_float(lane_shift(__float_as_int(v), 0x138)); }
-__device__ __forceinline__ double shift_d(double v, int ctrl) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = static_cast<uint32_t>(lane_shift(static_cast<int>(b), ctrl));
-    const uint32_t hi = static_cast<uint32_t>(lane_shift(static_cast<int>(b >> 32), ctrl));
-    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
-}
-__device__ __forceinline__ double from_right(double v) { return shift_d(v, 0x130); }
-__device__ __forceinline__ double from_left(double v) { return shift_d(v, 0x138); }
+// Value of lane l + 1 (from_right) or l - 1 (from_left) of the wave, 0 past
+// the wave's ends (lane shifts of common.hpp: uniform control flow only).
+template <class V> __device__ __forceinline__ V from_right(V v) { return lane_next(v, V(0)); }
+template <class V> __device__ __forceinline__ V from_left(V v) { return lane_prev(v, V(0)); }
 
 template <class T, int TJ, int PF>
 __global__ __launch_bounds__(256) void k_hdiff_adjoint_dpp(AdjArgs p, int nbi, int nstrips, int kc) {

@@ -56,6 +56,38 @@ template <> struct Storage<uint16_t> {
     static __device__ __forceinline__ void store_d(uint16_t *p, double v) { *p = round_d(v); }
 };
 
+// ---------------------------------------------------------------------------
+// Whole-wave lane shifts (DPP wave_shl / wave_shr by one lane): lane_next
+// gives lane l the value of lane l + 1, lane_prev that of lane l - 1; the
+// lane at the end with no such neighbour (63, resp. 0) gets `edge`.  A lane
+// disabled in EXEC supplies no value, so a shift is only meaningful while the
+// whole wave is active: callers shift in uniform control flow, never inside an
+// operand of ?: (which is evaluated conditionally, so the compiler may branch
+// around it), and the empty asm keeps the compiler from sinking a shift into
+// the branch of a conditional store that uses it.
+// ---------------------------------------------------------------------------
+constexpr int DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t lane_move(uint32_t v, uint32_t edge) {
+    int r = __builtin_amdgcn_update_dpp(static_cast<int>(edge), static_cast<int>(v), CTRL, 0xf, 0xf, false);
+    asm volatile("" : "+v"(r));
+    return static_cast<uint32_t>(r);
+}
+template <int CTRL>
+__device__ __forceinline__ float lane_move(float v, float edge) {
+    return __uint_as_float(lane_move<CTRL>(__float_as_uint(v), __float_as_uint(edge)));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_move(double v, double edge) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v), e = __builtin_bit_cast(uint64_t, edge);
+    const uint32_t lo = lane_move<CTRL>(static_cast<uint32_t>(b), static_cast<uint32_t>(e));
+    const uint32_t hi = lane_move<CTRL>(static_cast<uint32_t>(b >> 32), static_cast<uint32_t>(e >> 32));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+template <class V> __device__ __forceinline__ V lane_next(V v, V edge) { return lane_move<DPP_WAVE_SHL1>(v, edge); }
+template <class V> __device__ __forceinline__ V lane_prev(V v, V edge) { return lane_move<DPP_WAVE_SHR1>(v, edge); }
+
 // Resident workgroups of a kernel with `block` threads on the current device
 // (host side; 0 if the runtime cannot say).
 int resident_workgroups(const void *kernel, int block);

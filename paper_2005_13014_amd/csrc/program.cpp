@@ -380,6 +380,7 @@ int build_plan(const stencil_program_t *prog, int dtype, int tj, int fpw, char *
         int tiles = 0;
         auto flush = [&]() {
             if (hb.nsub > 0) {
+                hb.kc = HGRAD_RUN;
                 hb.beta_h = prog->beta_h;
                 hb.beta_v = prog->beta_v;
                 plan->hg.push_back(hb);
@@ -399,6 +400,8 @@ int build_plan(const stencil_program_t *prog, int dtype, int tj, int fpw, char *
                 h.sj = static_cast<int>(cf.sj); h.sk = static_cast<int>(cf.sk);
                 h.nbi = (cf.ni + 63) / 64;
                 h.nbj = (cf.nj + HGRAD_ROWS - 1) / HGRAD_ROWS;
+                h.ngroups = (h.nbi * h.nbj + 3) / 4;
+                h.nruns = (cf.nk + HGRAD_RUN - 1) / HGRAD_RUN;
                 h.nfields = sd.nfields - f0 < BATCH_FIELDS ? sd.nfields - f0 : BATCH_FIELDS;
                 h.tile0 = tiles;
                 h.y_bytes = static_cast<uint32_t>(((cf.ni + 1) + (cf.nj + 1) * cf.sj + (cf.nk - 1) * cf.sk + 1) * es);
@@ -407,7 +410,7 @@ int build_plan(const stencil_program_t *prog, int dtype, int tj, int fpw, char *
                     h.y[f] = ys[s][f0 + f];
                     h.z[f] = sd.z[f0 + f].origin;
                 }
-                tiles += h.nbi * h.nbj * h.nfields;
+                tiles += h.ngroups * h.nruns * h.nfields;
             }
         }
         flush();

@@ -11,113 +11,139 @@ namespace stl {
 // z = y - beta_h ((y(i+1) - y(i-1))/2 + (y(j+1) - y(j-1))/2) - beta_v Dk y,
 // Dk y = (y(k+1) - y(k-1))/2 inside the column, y(1) - y(0) at the bottom and
 // y(K-1) - y(K-2) at the top (0 for a single level).  y carries a 1-cell halo.
-constexpr int HGRAD_ROWS = 4;  // rows of an hgrad tile, one wave each (8 measured no faster)
+constexpr int HGRAD_ROWS = 8;  // rows of an hgrad strip (16 measured slower)
+constexpr int HGRAD_RUN = 32;  // levels per wave (a run of consecutive levels)
 
 struct HgradSub {
     const void *y[BATCH_FIELDS];  // interior origins
     void *z[BATCH_FIELDS];
     int I, J, K, sj, sk;
-    int nbi, nbj, tile0, nfields;
+    int nbi, nbj, ngroups, nruns, tile0, nfields;
     uint32_t y_bytes, z_bytes;  // addressable bytes from y's cell (-1, -1, 0) and from z's origin
 };
 
 struct HgradBatch {
     HgradSub sub[BATCH_SUBS];
-    int nsub;
+    int nsub, kc;
     double beta_h, beta_v;
 };
 
-// One 64 x TR tile of one field per workgroup (one wave per row), marching k.
-// Per level the tile's y rows j0 - 1 .. j0 + TR and its side columns i0 - 1, i0 + 64 are
-// staged in LDS (each wave loads its own row, which holds its centre values;
-// waves 0 and 1 also load the rows above and below the tile, wave 2 the side
-// columns), the horizontal neighbours are read from the tile and the vertical
-// ones are kept in registers.  Loads run PF levels ahead.
-template <class T, int TR = HGRAD_ROWS, int PF = 8>
-__global__ __launch_bounds__(64 * TR) void k_hgrad_batch(HgradBatch b) {
-    static_assert(PF % 2 == 0, "the LDS tile alternates with the ring slot");
-    static_assert(TR >= 3 && 2 * (TR + 2) <= 64, "wave 2 stages both side columns of every tile row");
+// Register strips: one wave per strip of 64 columns x TJ rows of one field,
+// marching a run of kc levels; four independent waves per workgroup (no LDS,
+// no barrier).  Workgroups are numbered per subdomain field-major, then run,
+// then strip group, so that neighbouring strips share an XCD's L2.  At each
+// level a lane holds its column's y on the strip's rows j0 - 1 .. j0 + TJ;
+// y(i +- 1) comes from the neighbouring lanes, and for the strip's end lanes
+// from one more load per row (lanes 0..31 load y(i0 - 1), lanes 32..63
+// y(i0 + 64), the value the end lane is given by the shift; one load per row
+// and level measured faster than one per level read out lane by lane);
+// y(j +- 1) is the row above or below and y(k +- 1) the previous or next
+// level's row.  The next PF levels are requested before a level is computed.
+// Cells are clamped into [-1, I] x [-1, J] x [0, K), which only values that
+// are never used can reach.
+template <class T, int TJ, int PF>
+__global__ __launch_bounds__(256) void k_hgrad_strip(HgradBatch b) {
+#pragma clang fp contract(off)
     using S = Storage<T>;
     using C = typename S::C;
     using IO = BufIO<T>;
-    constexpr int PI = 68, ROWS = TR + 2, TILE = ROWS * PI;
+    using R = typename IO::R;
+    constexpr int NR = TJ + 2;
     constexpr uint32_t ES = sizeof(T);
-    __shared__ C tile[2 * TILE];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     int s = 0;
     while (s + 1 < b.nsub && b.sub[s + 1].tile0 <= t) ++s;
     const HgradSub &sb = b.sub[s];
     const int local = t - sb.tile0;
-    const int f = local % sb.nfields, tl = local / sb.nfields;
-    const int bi = tl % sb.nbi, bj = tl / sb.nbi;
-    const int tid = threadIdx.x, ti = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int I = sb.I, J = sb.J, sj = sb.sj, K = sb.K;
-    const int i0 = bi * 64, j0 = bj * TR;
-    const int gi = i0 + ti, gj = j0 + w;
-    const bool active = gi < I && gj < J;
-    // y is addressed from its cell (-1, -1, 0); cells are clamped into
-    // [-1, I] x [-1, J], which only lanes that store nothing can reach.
-    const auto ry = make_rsrc(static_cast<const char *>(sb.y[f]) - (1 + sj) * static_cast<int>(ES), sb.y_bytes);
+    const int group = local % sb.ngroups, rest = local / sb.ngroups;
+    const int run = rest % sb.nruns, f = rest / sb.nruns;
+    const int strip = group * 4 + __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    if (strip >= sb.nbi * sb.nbj) return;
+    const int I = sb.I, J = sb.J, K = sb.K;
+    const uint32_t sj = static_cast<uint32_t>(sb.sj), skb = static_cast<uint32_t>(sb.sk) * ES;
+    const int k0 = run * b.kc, k1 = min(K, k0 + b.kc);
+    const int i0 = (strip % sb.nbi) * 64, j0 = (strip / sb.nbi) * TJ;
+    const int lane = threadIdx.x & 63, gi = i0 + lane;
+    const bool active_i = gi < I;
+    // y from its cell (-1, -1, 0): a lane's own column and its end value.
+    const auto ry = make_rsrc(static_cast<const char *>(sb.y[f]) - (1 + sb.sj) * static_cast<int>(ES), sb.y_bytes);
     const auto rz = make_rsrc(sb.z[f], sb.z_bytes);
-    auto voff = [&](int i, int j) {
-        return static_cast<uint32_t>(min(max(i, -1), I) + 1 + (min(max(j, -1), J) + 1) * sj) * ES;
+    const uint32_t v_own = static_cast<uint32_t>(min(gi, I) + 1) * ES;
+    const uint32_t v_end = static_cast<uint32_t>(min(lane < 32 ? i0 - 1 : i0 + 64, I) + 1) * ES;
+    const uint32_t v_z = static_cast<uint32_t>(min(gi, I - 1)) * ES;
+    auto row = [&](int r) {  // byte offset of y row j0 - 1 + r (uniform)
+        return static_cast<uint32_t>(min(j0 - 1 + r, J) + 1) * sj * ES;
     };
-    const uint32_t v_own = voff(gi, gj);
-    // Second row: wave 0 the row above the tile (tile row 0), wave 1 the row
-    // below it (tile row TR + 1), wave 2 the side columns (lanes 0 .. 2 ROWS - 1),
-    // the other waves none.
-    const int sr = ti >> 1, scol = (ti & 1) ? 65 : 0;  // side: tile row, tile column
-    const uint32_t v_two = w == 0 ? voff(gi, j0 - 1) : w == 1 ? voff(gi, j0 + TR) : voff(i0 - 1 + scol, j0 - 1 + min(sr, ROWS - 1));
-    const bool two = w < 2 || (w == 2 && ti < 2 * ROWS);
-    const int l_own = (w + 1) * PI + ti + 1;
-    const int l_two = w == 0 ? ti + 1 : w == 1 ? (TR + 1) * PI + ti + 1 : min(sr, ROWS - 1) * PI + scol;
-    const uint32_t vz = static_cast<uint32_t>(min(gi, I - 1) + min(gj, J - 1) * sj) * ES;
-    const uint32_t skb = static_cast<uint32_t>(sb.sk) * ES;
+    auto lev = [&](int k) { return static_cast<uint32_t>(min(max(k, 0), K - 1)) * skb; };
 
-    // Register ring of the next PF levels (raw stored bits, widened where
-    // used): slot q holds level k with k % PF == q.
-    using R = typename IO::R;
-    R own[PF], tw[PF];
-    // Levels past the top are clamped to it (their values are never used),
-    // so no load sits behind a branch whose join would wait for it.
+    // Ring of the next PF levels (raw stored bits): slot q holds level
+    // k0 + 1 + q + m PF.
+    R ring[PF][NR], rend[PF][TJ];
     auto load = [&](int q, int k) {
-        const uint32_t so = static_cast<uint32_t>(min(k, K - 1)) * skb;
-        own[q] = IO::load_raw(ry, v_own, so);
-        tw[q] = IO::load_raw(ry, v_two, so);
-    };
+        const uint32_t so = lev(k);
 #pragma unroll
-    for (int q = 0; q < PF; ++q) load(q, q);
+        for (int r = 0; r < NR; ++r) ring[q][r] = IO::load_raw(ry, v_own, row(r) + so);
+#pragma unroll
+        for (int r = 0; r < TJ; ++r) rend[q][r] = IO::load_raw(ry, v_end, row(r + 1) + so);
+    };
+    C dn[TJ], cur[NR], end[TJ];
+    {
+        R d0[TJ], c0[NR], e0[TJ];
+#pragma unroll
+        for (int r = 0; r < TJ; ++r) d0[r] = IO::load_raw(ry, v_own, row(r + 1) + lev(k0 - 1));
+#pragma unroll
+        for (int r = 0; r < NR; ++r) c0[r] = IO::load_raw(ry, v_own, row(r) + lev(k0));
+#pragma unroll
+        for (int r = 0; r < TJ; ++r) e0[r] = IO::load_raw(ry, v_end, row(r + 1) + lev(k0));
+#pragma unroll
+        for (int q = 0; q < PF; ++q) load(q, k0 + 1 + q);
+#pragma unroll
+        for (int r = 0; r < TJ; ++r) {
+            dn[r] = IO::cvt(d0[r]);
+            end[r] = IO::cvt(e0[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cur[r] = IO::cvt(c0[r]);
+    }
 
     const C bh = static_cast<C>(b.beta_h), bv = static_cast<C>(b.beta_v), half = C(0.5);
-    C y_dn = C(0), y_c = IO::cvt(own[0]);
-    for (int k0 = 0; k0 < K; k0 += PF) {
+    for (int kk = k0; kk < k1; kk += PF) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
-            const int k = k0 + q;
-            if (k >= K) break;
-            C *tb = &tile[(q & 1) * TILE];  // PF is even: q & 1 == k & 1
-            tb[l_own] = IO::cvt(own[q]);
-            if (two) tb[l_two] = IO::cvt(tw[q]);
-            const C y_up = k + 1 < K ? IO::cvt(own[(q + 1) % PF]) : C(0);
-            load(q, k + PF);
-            __syncthreads();
-            const C *c = &tb[(w + 1) * PI + ti + 1];
-            const C gi_ = half * (c[1] - c[-1]);
-            const C gj_ = half * (c[PI] - c[-PI]);
-            C gk;
-            if (K == 1)
-                gk = C(0);
-            else if (k == 0)
-                gk = y_up - y_c;
-            else if (k == K - 1)
-                gk = y_c - y_dn;
-            else
-                gk = half * (y_up - y_dn);
-            const C z = y_c - bh * (gi_ + gj_) - bv * gk;
-            if (active) IO::template store_d<2>(rz, vz, static_cast<uint32_t>(k) * skb, static_cast<double>(z));
-            y_dn = y_c;
-            y_c = y_up;
+            const int k = kk + q;
+            if (k >= k1) break;
+            C up[TJ];
+#pragma unroll
+            for (int r = 0; r < TJ; ++r) up[r] = IO::cvt(ring[q][r + 1]);
+            const uint32_t so = static_cast<uint32_t>(k) * skb;
+#pragma unroll
+            for (int r = 0; r < TJ; ++r) {
+                const C yc = cur[r + 1];
+                const C ye = lane_next(yc, end[r]), yw = lane_prev(yc, end[r]);
+                const C gi_ = half * (ye - yw);
+                const C gj_ = half * (cur[r + 2] - cur[r]);
+                C gk;
+                if (K == 1)
+                    gk = C(0);
+                else if (k == 0)
+                    gk = up[r] - yc;
+                else if (k == K - 1)
+                    gk = yc - dn[r];
+                else
+                    gk = half * (up[r] - dn[r]);
+                const C z = yc - bh * (gi_ + gj_) - bv * gk;
+                const int j = j0 + r;
+                if (active_i && j < J)
+                    IO::template store_d<2>(rz, v_z, static_cast<uint32_t>(j) * sj * ES + so, static_cast<double>(z));
+            }
+#pragma unroll
+            for (int r = 0; r < TJ; ++r) {
+                dn[r] = cur[r + 1];
+                end[r] = IO::cvt(rend[q][r]);
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) cur[r] = IO::cvt(ring[q][r]);
+            if (k + 1 + PF <= k1) load(q, k + 1 + PF);
         }
     }
 }
@@ -136,7 +162,8 @@ static hipError_t launch_column_batch_t(const ColumnBatch &b, int ntiles, hipStr
 
 template <class T>
 static hipError_t launch_hgrad_batch_t(const HgradBatch &b, int ntiles, hipStream_t st) {
-    hipLaunchKernelGGL((k_hgrad_batch<T>), dim3(ntiles), dim3(64 * HGRAD_ROWS), 0, st, b);
+    // 4 levels in flight (2: 335 us, 4: 328 us for the 6 x 8 FP32 step); FP64 2, for its registers.
+    hipLaunchKernelGGL((k_hgrad_strip<T, HGRAD_ROWS, sizeof(T) == 8 ? 2 : 4>), dim3(ntiles), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 
