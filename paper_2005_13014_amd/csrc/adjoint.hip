@@ -704,13 +704,15 @@ static hipError_t adjoint_run(AdjArgs a, void *scratch, bool staged_hdiff, int s
         // 256 x 256 x 80 FP32: reverse pass 0.0704 ms against 0.0722 for 8
         // rows and two levels, 0.0747 for 8 and one, 0.0754 for 16 and one);
         // FP64 4 rows and one level (its values take twice the registers).
-        const bool f64 = std::is_same<T, double>::value;
+        constexpr bool f64 = std::is_same<T, double>::value;
         const int tj = strip_rows ? strip_rows : f64 ? 4 : 12, pf = strip_prefetch ? strip_prefetch : 1;
         if (tj == 4 && pf == 1) return launch_hdiff_adjoint_dpp<T, 4, 1>(a, st);
         if (tj == 4 && pf == 2) return launch_hdiff_adjoint_dpp<T, 4, 2>(a, st);
-        if (!f64 && tj == 8 && pf == 1) return launch_hdiff_adjoint_dpp<T, 8, 1>(a, st);
-        if (!f64 && tj == 8 && pf == 2) return launch_hdiff_adjoint_dpp<T, 8, 2>(a, st);
-        if (!f64 && tj == 12 && pf == 1) return launch_hdiff_adjoint_dpp<T, 12, 1>(a, st);
+        if constexpr (!f64) {
+            if (tj == 8 && pf == 1) return launch_hdiff_adjoint_dpp<T, 8, 1>(a, st);
+            if (tj == 8 && pf == 2) return launch_hdiff_adjoint_dpp<T, 8, 2>(a, st);
+            if (tj == 12 && pf == 1) return launch_hdiff_adjoint_dpp<T, 12, 1>(a, st);
+        }
         return hipErrorInvalidValue;
     }
     // The LDS formulation: rows per tile 8 (two per thread) where the staged
