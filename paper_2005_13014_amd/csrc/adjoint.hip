@@ -58,7 +58,7 @@ struct AdjArgs {
 // (which visits the levels in the forward kernel's order) from a u tile
 // staged in LDS per level, and kept in LDS for the outward walk, instead of
 // being read from a separately computed scratch field.
-template <class T, int TJ, int PF, int KH, bool MATRIX, bool FUSEH>
+template <class T, int TJ, int PF, int KH, bool MATRIX, bool FUSEH, int WR>
 __global__ __launch_bounds__(128 * TJ) __attribute__((amdgpu_waves_per_eu(2, 8))) void
 k_vadv_adjoint(AdjArgs p, int nbi) {
 #pragma clang fp contract(off)
@@ -221,7 +221,6 @@ k_vadv_adjoint(AdjArgs p, int nbi) {
     const bool other = K - M > 0;  // the interface level has a neighbour across it
     const auto rx = make_rsrc(MATRIX ? p.x : p.w, tbytes);
     // wcon, h (and x) of local level t: a ring of the next WR levels out.
-    constexpr int WR = 4;
     double rwc_[WR], rh_[WR], rx_[WR];
     auto wload = [&](int q, int t) {
         const uint32_t k = clampk(t);
@@ -644,15 +643,20 @@ size_t adjoint_scratch_bytes(int dtype, int sk, int K) {
 
 template <class T, int KH, bool FUSEH>
 static void launch_vadv_adjoint_t(const AdjArgs &a, hipStream_t st) {
-    // 64 x 2 tiles (64 x 4 and 64 x 1 measured no faster); the outward walk
-    // prefetches 2 levels with h evaluated in-kernel (4 and 8 slower), else 4.
-    constexpr int TJ = 2, PF = FUSEH ? 2 : 4;
+    // 64 x 2 tiles (64 x 4 and 64 x 1 measured no faster).  The elimination
+    // prefetches PF levels (2 while it also stages the u tile: 4 and 8 were
+    // slower), the outward walk WR levels: at 256 x 256 x 80 FP32 a grid of
+    // one round runs every workgroup's walk at once, and the walk took 17.7 us
+    // of the kernel's 40.9 with WR = 4, 13.2 with 8, 11.3 with 16 (12 and 24
+    // slower than 16).  FP64 keeps 4: its ring also holds h, and with the
+    // matrix gradients x, two registers each a slot (8 spills at KH = 48).
+    constexpr int TJ = 2, PF = FUSEH ? 2 : 4, WR = FUSEH ? 16 : 4;
     const int nbi = (a.I + 63) / 64, nbj = (a.J + TJ - 1) / TJ;
     if (a.ga || a.gb || a.gc)
-        hipLaunchKernelGGL((k_vadv_adjoint<T, TJ, PF, KH, true, FUSEH>), dim3(nbi * nbj), dim3(128 * TJ), 0, st,
-                           a, nbi);
+        hipLaunchKernelGGL((k_vadv_adjoint<T, TJ, PF, KH, true, FUSEH, WR>), dim3(nbi * nbj), dim3(128 * TJ), 0,
+                           st, a, nbi);
     else
-        hipLaunchKernelGGL((k_vadv_adjoint<T, TJ, PF, KH, false, FUSEH>), dim3(nbi * nbj), dim3(128 * TJ), 0,
+        hipLaunchKernelGGL((k_vadv_adjoint<T, TJ, PF, KH, false, FUSEH, WR>), dim3(nbi * nbj), dim3(128 * TJ), 0,
                            st, a, nbi);
 }
 
