@@ -588,6 +588,11 @@ PMC_CMD = ("cd /tmp && TMPDIR=/tmp timeout -s KILL 120 rocprofv3 --pmc {c} --out
 COPY_PROBE_BYTES = 1 << 30
 
 
+def kernel_name(name):
+    """A traced kernel's name without its parameter list."""
+    return name.replace("(anonymous namespace)::", "").split("(")[0]
+
+
 def summarize_profiles(outdir):
     """Writes profiles/k_column_f32_512x512x80_trace.md from the kernel trace
     under outdir/prof_trace and, if the FETCH_SIZE / WRITE_SIZE runs are
@@ -600,7 +605,7 @@ def summarize_profiles(outdir):
         return hits[0] if hits else None
 
     def short(name):
-        return name.split("(")[0][:100]
+        return kernel_name(name)[:100]
 
     rows = list(csv.DictReader(open(one("prof_trace/**/*kernel_stats.csv"))))
     cols = [r for r in rows if "k_column" in r["Name"]]
@@ -694,7 +699,7 @@ def summarize_variant(outdir, name, fetch_calibration):
         out = {}
         for r in csv.DictReader(open(f)) if f else []:
             if r.get("Counter_Name") == cname:
-                out.setdefault(r["Kernel_Name"].split("(")[0], []).append(float(r["Counter_Value"]))
+                out.setdefault(kernel_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
         return {k: sum(v) / len(v) for k, v in out.items()}
 
     rows = list(csv.DictReader(open(one("v_%s_trace/**/*kernel_stats.csv" % name))))
@@ -708,7 +713,7 @@ def summarize_variant(outdir, name, fetch_calibration):
     md += ["```", "", "| kernel | calls | average (us) | HBM read (MB) | HBM write (MB) | GB/s |",
            "|---|---|---|---|---|---|"]
     for r in rows:
-        n = r["Name"].split("(")[0]
+        n = kernel_name(r["Name"])
         if "stl::" not in n:
             continue
         us = float(r["AverageNs"]) / 1e3

@@ -649,7 +649,8 @@ static void launch_vadv_adjoint_t(const AdjArgs &a, hipStream_t st) {
     // one round runs every workgroup's walk at once, and the walk took 17.7 us
     // of the kernel's 40.9 with WR = 4, 13.2 with 8, 11.3 with 16 (12 and 24
     // slower than 16).  FP64 keeps 4: its ring also holds h, and with the
-    // matrix gradients x, two registers each a slot (8 spills at KH = 48).
+    // matrix gradients x, two registers each a slot (8 spills at KH = 48;
+    // without them, 8 measured 1% slower).
     constexpr int TJ = 2, PF = FUSEH ? 2 : 4, WR = FUSEH ? 16 : 4;
     const int nbi = (a.I + 63) / 64, nbj = (a.J + TJ - 1) / TJ;
     if (a.ga || a.gb || a.gc)
