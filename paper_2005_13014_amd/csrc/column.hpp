@@ -273,12 +273,12 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     const int half = __builtin_amdgcn_readfirstlane(tid >= NH ? 1 : 0);
     const int l = tid - half * NH, ti = l & 63;
     const int tj = __builtin_amdgcn_readfirstlane(l >> 6);
-    const int i0 = bi * TI, j0 = bj * TJ;
+    const int i0 = p.i_lo + bi * TI, j0 = bj * TJ;
     const int gi = i0 + ti, gj = j0 + tj;
-    const bool active = gi < p.I && gj < p.J;
+    const bool active = gi >= 0 && gi < p.I && gj < p.J;
     const int I = p.I, J = p.J, K = p.K, sj = p.sj;
     // Lanes past a ragged edge read a valid column and store nothing.
-    const uint32_t vcol = static_cast<uint32_t>(min(gi, I - 1) + min(gj, J - 1) * sj) * ES;
+    const uint32_t vcol = static_cast<uint32_t>(min(max(gi, 0), I - 1) + min(gj, J - 1) * sj) * ES;
     const uint32_t sk_bytes = static_cast<uint32_t>(p.sk) * ES;
 
     const auto ru = make_rsrc(p.u, FUSED ? p.u_bytes : p.col_bytes);
@@ -302,7 +302,7 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
         const int r = tj + m * TJ;
-        const int gx = min(gi, I + 1), gy = min(j0 - 2 + r, J + 1);
+        const int gx = min(max(gi, -2), I + 1), gy = min(j0 - 2 + r, J + 1);
         vmain[m] = static_cast<uint32_t>(gx + 2 + (gy + 2) * sj) * ES;
         lmain[m] = r * PI + ti + 2;
     }
@@ -310,7 +310,7 @@ __device__ __forceinline__ void column_tile(const ColumnArgs &p, int bi, int bj,
     const int sr = min(l >> 2, PJ - 1), sq = l & 3;
     const int sc = sq < 2 ? sq : sq + 64;
     const uint32_t vside =
-        static_cast<uint32_t>(min(i0 - 2 + sc, I + 1) + 2 + (min(j0 - 2 + sr, J + 1) + 2) * sj) * ES;
+        static_cast<uint32_t>(min(max(i0 - 2 + sc, -2), I + 1) + 2 + (min(j0 - 2 + sr, J + 1) + 2) * sj) * ES;
     const int lside = l < 4 * PJ ? sr * PI + sc : PJ * PI + ti;
 
     // Both halves run KH steps.  A half with nsteps < KH levels starts with
@@ -500,16 +500,17 @@ __device__ __forceinline__ void column_tile_pipe(const ColumnArgs &p, int first,
     uint32_t vmain[MR], vside = 0, vcol = 0;
     bool active = false;
     auto locate = [&](int t) {
-        const int i0 = (t % p.nbi) * TI, j0 = (t / p.nbi) * TJ;
+        const int i0 = p.i_lo + (t % p.nbi) * TI, j0 = (t / p.nbi) * TJ;
         const int gi = i0 + ti, gj = j0 + tj;
-        active = gi < I && gj < J;
-        vcol = static_cast<uint32_t>(min(gi, I - 1) + min(gj, J - 1) * sj) * ES;
+        active = gi >= 0 && gi < I && gj < J;
+        vcol = static_cast<uint32_t>(min(max(gi, 0), I - 1) + min(gj, J - 1) * sj) * ES;
 #pragma unroll
         for (int m = 0; m < MR; ++m) {
-            const int gx = min(gi, I + 1), gy = min(j0 - 2 + tj + m * TJ, J + 1);
+            const int gx = min(max(gi, -2), I + 1), gy = min(j0 - 2 + tj + m * TJ, J + 1);
             vmain[m] = static_cast<uint32_t>(gx + 2 + (gy + 2) * sj) * ES;
         }
-        vside = static_cast<uint32_t>(min(i0 - 2 + sc, I + 1) + 2 + (min(j0 - 2 + sr, J + 1) + 2) * sj) * ES;
+        vside = static_cast<uint32_t>(min(max(i0 - 2 + sc, -2), I + 1) + 2 + (min(j0 - 2 + sr, J + 1) + 2) * sj) *
+                ES;
     };
 
     const int M = (K + 1) >> 1;

@@ -167,6 +167,9 @@ struct ColumnArgs {
     int I, J, K, sj, sk;
     int nbi, nbj;
     double dt;
+    // First column of the first tile (0, or negative so that tiles start on
+    // 128-byte lines); columns outside [0, I) are read clamped, never stored.
+    int i_lo;
 };
 
 }  // namespace stl

@@ -310,6 +310,24 @@ ColumnArgs column_args_ext(const stencil_field_t &cf, const stencil_subdomain_t 
     return a;
 }
 
+// First column of a subdomain's first column-kernel tile, in the coordinates
+// of its domain grown by e: a tile that starts at the start of a 128-byte line
+// of the coefficient fields reads each tile row of every field in whole lines
+// (a tile starting one element into a line touches one more line per row), so
+// the tiles start on the last line start at or before the domain's first
+// column, unless that takes more tiles than starting at column 0.
+int tile_origin(const stencil_field_t &cf, int e, long long es) {
+    const long long L = 128 / es;
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(cf.origin);
+    if (addr % static_cast<uintptr_t>(es) != 0) return 0;
+    const long long a = static_cast<long long>((addr / es) % L);  // interior column 0 is element a of its line
+    long long first = -a;                                         // interior column of a line start
+    while (first > -e) first -= L;
+    const int lo = static_cast<int>(first) + e;
+    const int I = cf.ni + 2 * e;
+    return (I - lo + 63) / 64 <= (I + 63) / 64 ? lo : 0;
+}
+
 // Builds the launch tables for a given column-kernel tile height and number
 // of fields per workgroup.  Scratch offsets for y are laid out when
 // `scratch` is null (sizing pass).
@@ -328,11 +346,16 @@ int build_plan(const stencil_program_t *prog, int dtype, int tj, int fpw, char *
     for (int s = 0; s < prog->nsub; ++s) {
         const stencil_subdomain_t &sd = prog->sub[s];
         if (!plan->hgrad || empty(&sd.coeff) || sd.nfields == 0) continue;
+        // y's origin at least one row and one column in, so the 1-cell ring is
+        // addressable, and placed so that the column tiles' rows of y start on
+        // 128-byte lines, as their rows of the input fields do (tile_origin).
+        const int lo = tile_origin(sd.coeff, e, es);
+        const long long ring = (sd.coeff.sj + 1) * es;
+        const long long want = ((-(lo - e) * es) % 128 + 128) % 128;
+        const long long pad = ring + ((want - ring % 128) % 128 + 128) % 128;
         for (int f = 0; f < sd.nfields; ++f) {
-            const size_t bytes = static_cast<size_t>((static_cast<long long>(sd.coeff.nk) * sd.coeff.sk +
-                                                      2 * (sd.coeff.sj + 1)) * es);
-            // origin one row and one column in, so the 1-cell ring is addressable
-            ys[s].push_back(scratch ? scratch + off + (sd.coeff.sj + 1) * es : nullptr);
+            const size_t bytes = static_cast<size_t>(static_cast<long long>(sd.coeff.nk) * sd.coeff.sk * es + pad + ring);
+            ys[s].push_back(scratch ? scratch + off + pad : nullptr);
             off += (bytes + 255) / 256 * 256;
         }
     }
@@ -356,7 +379,9 @@ int build_plan(const stencil_program_t *prog, int dtype, int tj, int fpw, char *
         for (int s = 0; s < prog->nsub; ++s) {
             const stencil_subdomain_t &sd = prog->sub[s];
             if (empty(&sd.coeff) || sd.nfields == 0 || kh_bucket(sd.coeff.nk) != bucket) continue;
-            const ColumnArgs a = column_args_ext(sd.coeff, sd, e, prog->dt, tj);
+            ColumnArgs a = column_args_ext(sd.coeff, sd, e, prog->dt, tj);
+            a.i_lo = tile_origin(sd.coeff, e, es);
+            a.nbi = (a.I - a.i_lo + 63) / 64;
             const long long shift = (e + e * sd.coeff.sj) * es;
             for (int f0 = 0; f0 < sd.nfields; f0 += BATCH_FIELDS) {
                 if (cl.b.nsub == BATCH_SUBS) flush();

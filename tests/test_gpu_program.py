@@ -166,6 +166,40 @@ def test_pipelined_and_staged_column_stages_agree(stages):
     assert worst <= TOL["f32"]
 
 
+def shifted(field, by):
+    """The same field in a fresh buffer whose interior origin sits `by`
+    elements later (so it no longer starts on a 128-byte line)."""
+    buf = torch.full((field.buf.numel() + 64,), -9.0, dtype=field.buf.dtype, device=field.buf.device)
+    buf[by:by + field.buf.numel()] = field.buf
+    return B.Field(buf, field.origin + by, field.ni, field.nj, field.nk, field.hi, field.hj, field.sj,
+                   field.sk, field.dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64", "bf16"])
+def test_column_tiles_follow_the_field_alignment(dtype):
+    """The column tiles start on 128-byte lines of the coefficient fields when
+    that takes no extra tile; fields whose origins sit elsewhere in a line give
+    bitwise the results of line-aligned ones (each column is computed the same
+    way whichever tile holds it), with and without the horizontal stage."""
+    shapes = ((320, 9, 84), (70, 13, 9), (128, 6, 40), (5, 3, 1))
+    data = small_data(dtype, nfields=2, shapes=shapes)
+    for stages in (FULL, B.STAGE_HDIFF | B.STAGE_VADV | B.STAGE_VDIFF):
+        subs = device_program(data, dtype)
+        run(subs, stages)
+        ref = [[z.to_numpy() for z in s["z"]] for s in subs]
+        for by in (1, 3, 17):
+            moved = [{n: (shifted(v, by) if n not in ("u", "z") else [shifted(f, by) for f in v])
+                      for n, v in s.items()} for s in subs]
+            for s in moved:
+                for z in s["z"]:
+                    z.buf.fill_(-7.0)
+            run(moved, stages)
+            for s, r in zip(moved, ref):
+                for z, rr in zip(s["z"], r):
+                    assert np.array_equal(z.to_numpy(), rr), (stages, by)
+                    assert halo_untouched(z)
+
+
 def test_tables_split_over_many_subdomains_and_fields():
     # 10 subdomains (more than one table) and 11 fields (more than one entry).
     shapes = tuple((17 + 3 * q, 6 + q, 5 + q) for q in range(10))
