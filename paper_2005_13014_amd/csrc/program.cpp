@@ -84,7 +84,9 @@ std::vector<Variant> variants_for(int dtype, bool staged_only) {
 
 int kh_bucket(int K) {
     const int m = (K + 1) / 2;
-    return m <= 16 ? 16 : m <= 32 ? 32 : m <= 40 ? 40 : 48;
+    for (int kh : PROGRAM_BUCKETS)
+        if (m <= kh) return kh;
+    return PROGRAM_BUCKETS[sizeof(PROGRAM_BUCKETS) / sizeof(PROGRAM_BUCKETS[0]) - 1];
 }
 
 // One batched launch of the column stages, and of hgrad.
@@ -361,7 +363,7 @@ int build_plan(const stencil_program_t *prog, int dtype, int tj, int fpw, char *
     }
     plan->scratch_bytes = off;
 
-    for (int bucket : {16, 32, 40, 48}) {
+    for (int bucket : PROGRAM_BUCKETS) {
         ColumnLaunch cl{};
         cl.kh = bucket;
         cl.tj_nbj_rows = tj;

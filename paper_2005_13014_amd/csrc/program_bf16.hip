@@ -10,6 +10,7 @@ static hipError_t by_levels(const ColumnBatch &b, int kh, int ntiles, hipStream_
     case 16: return launch_column_batch_t<uint16_t, VD, TJ, PF, 16, 2>(b, ntiles, st);
     case 32: return launch_column_batch_t<uint16_t, VD, TJ, PF, 32, 2>(b, ntiles, st);
     case 40: return launch_column_batch_t<uint16_t, VD, TJ, PF, 40, 2>(b, ntiles, st);
+    case 45: return launch_column_batch_t<uint16_t, VD, TJ, PF, 45, 2>(b, ntiles, st);
     case 48: return launch_column_batch_t<uint16_t, VD, TJ, PF, 48, 1>(b, ntiles, st);
     }
     return hipErrorInvalidValue;

@@ -10,6 +10,7 @@ static hipError_t by_levels(const ColumnBatch &b, int kh, int ntiles, hipStream_
     case 16: return launch_column_batch_t<float, VD, TJ, PF, 16, 2, PIPE>(b, ntiles, st);
     case 32: return launch_column_batch_t<float, VD, TJ, PF, 32, 2, PIPE>(b, ntiles, st);
     case 40: return launch_column_batch_t<float, VD, TJ, PF, 40, 2, PIPE>(b, ntiles, st);
+    case 45: return launch_column_batch_t<float, VD, TJ, PF, 45, 2, PIPE>(b, ntiles, st);
     case 48: return launch_column_batch_t<float, VD, TJ, PF, 48, 1, PIPE>(b, ntiles, st);
     }
     return hipErrorInvalidValue;

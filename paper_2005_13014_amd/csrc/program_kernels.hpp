@@ -11,6 +11,14 @@ namespace stl {
 // z = y - beta_h ((y(i+1) - y(i-1))/2 + (y(j+1) - y(j-1))/2) - beta_v Dk y,
 // Dk y = (y(k+1) - y(k-1))/2 inside the column, y(1) - y(0) at the bottom and
 // y(K-1) - y(K-2) at the top (0 for a single level).  y carries a 1-cell halo.
+// Register buckets of the batched column kernels: a half column of up to KH
+// levels is held in registers, and a shorter one pays KH - levels padding
+// steps (at the same cost as real ones).  Every bucket is a launch of its own
+// with its own ramp-up and tail (≈25 us for a few thousand workgroups), so
+// finer buckets pay only where they keep subdomains together: KH = 45 serves
+// nk 81..90 (84 and 90 levels in one launch, 3 and 0 padding steps).
+constexpr int PROGRAM_BUCKETS[] = {16, 32, 40, 45, 48};
+
 constexpr int HGRAD_ROWS = 8;  // rows of an hgrad strip (16 measured slower)
 constexpr int HGRAD_RUN = 32;  // levels per wave (a run of consecutive levels)
 

@@ -149,8 +149,9 @@ def test_autotune_does_not_change_results():
 def test_pipelined_and_staged_column_stages_agree(stages):
     """The column stages with the software-pipelined level loop (the default)
     and with the staged one (STENCIL_PROGRAM_STAGED) give the same bits, in
-    every register bucket (1 .. 90 levels, ragged tiles)."""
-    shapes = ((70, 13, 9), (40, 33, 17), (5, 3, 1), (64, 8, 40), (40, 9, 70), (20, 5, 90), (130, 7, 84))
+    every register bucket (1 .. 96 levels, ragged tiles)."""
+    shapes = ((70, 13, 9), (40, 33, 17), (5, 3, 1), (64, 8, 40), (40, 9, 70), (20, 5, 90), (130, 7, 84),
+              (33, 6, 91), (17, 4, 96))
     data = small_data("f32", nfields=3, shapes=shapes)
     subs = device_program(data, "f32")
     run(subs, stages)
