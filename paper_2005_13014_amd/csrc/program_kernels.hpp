@@ -20,7 +20,10 @@ namespace stl {
 constexpr int PROGRAM_BUCKETS[] = {16, 32, 40, 45, 48};
 
 constexpr int HGRAD_ROWS = 8;  // rows of an hgrad strip (16 measured slower)
-constexpr int HGRAD_RUN = 32;  // levels per wave (a run of consecutive levels)
+// Levels per wave: a run of consecutive levels (runs of 4, 6, 8, 16, 32 and 96
+// levels took 319, 309, 302, 308, 328 and 363 us for the 6 x 8 FP32 step:
+// short runs give more waves to hide latency, each run rereads two levels).
+constexpr int HGRAD_RUN = 8;
 
 struct HgradSub {
     const void *y[BATCH_FIELDS];  // interior origins
@@ -170,7 +173,7 @@ static hipError_t launch_column_batch_t(const ColumnBatch &b, int ntiles, hipStr
 
 template <class T>
 static hipError_t launch_hgrad_batch_t(const HgradBatch &b, int ntiles, hipStream_t st) {
-    // 4 levels in flight (2: 335 us, 4: 328 us for the 6 x 8 FP32 step); FP64 2, for its registers.
+    // 4 levels in flight (with runs of 8 levels 2, 3 and 4 measured within 1%); FP64 2, for its registers.
     hipLaunchKernelGGL((k_hgrad_strip<T, HGRAD_ROWS, sizeof(T) == 8 ? 2 : 4>), dim3(ntiles), dim3(256), 0, st, b);
     return hipGetLastError();
 }
