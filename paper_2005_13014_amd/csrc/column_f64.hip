@@ -31,8 +31,10 @@ static hipError_t pipelined(const ColumnArgs &a, hipStream_t st) {
                                   : launch_column_pipe_t<double, TJ, PF, 32, 1, NT, false, CHAIN>(a, st);
     if (m <= 40) return a.K == 80 ? launch_column_pipe_t<double, TJ, PF, 40, 1, NT, true, CHAIN>(a, st)
                                   : launch_column_pipe_t<double, TJ, PF, 40, 1, NT, false, CHAIN>(a, st);
-    return a.K == 96 ? launch_column_pipe_t<double, TJ, PF, 48, 1, NT, true, CHAIN>(a, st)
-                     : launch_column_pipe_t<double, TJ, PF, 48, 1, NT, false, CHAIN>(a, st);
+    // 48 levels: 64 x 4 tiles would spill registers to scratch; 64 x 2 (same bits).
+    constexpr int TJ48 = TJ > 2 ? 2 : TJ;
+    return a.K == 96 ? launch_column_pipe_t<double, TJ48, PF, 48, 1, NT, true, CHAIN>(a, st)
+                     : launch_column_pipe_t<double, TJ48, PF, 48, 1, NT, false, CHAIN>(a, st);
 }
 
 // Four lanes per column: segments of ceil(nk / 4) <= KH levels, nk >= 8,
@@ -51,6 +53,7 @@ static const ColumnEntry kFused[] = {
     {2, 4, false, 1, staged<true, 2, 4, false>},
     {2, 2, true, 1, staged<true, 2, 2, true>},
     {2, 2, true, 2, pipelined<2, 2, true, false>},
+    {4, 2, true, 2, pipelined<4, 2, true, false>},
 };
 
 bool column_variant_f64(const ColumnVariant &v) {
