@@ -79,7 +79,7 @@ def test_jvp_fp64_matches_oracle(shape):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-@pytest.mark.parametrize("shape", [(64, 64, 60), (99, 17, 33), (130, 5, 80)])
+@pytest.mark.parametrize("shape", [(64, 64, 60), (99, 17, 33), (130, 5, 80), (131, 9, 96), (3, 2, 1)])
 def test_jvp_low_precision_under_its_own_masks(dtype, shape):
     # As for the adjoint: the tangent jumps where a limiter decision flips, so
     # the reference takes the decisions of the kernel's arithmetic.
