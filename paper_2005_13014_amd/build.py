@@ -140,14 +140,17 @@ def resources(jobs: int | None = None) -> list:
 # default variants), marked in the report.
 MEASURED = {
     "k_column_pipe<float, 4, 4, 40, 2, true, true, false, 64>": "fused FP32 512x512x80 (headline), 256x256x80",
-    "k_column_pipe<double, 2, 2, 40, 1, true, true, false, 64>": "fused FP64 512x512x80",
-    "k_column_batch_pipe<float, 1, 2, 4, 48, 1>": "timestep 6x8, KH 48",
+    "k_column_pipe<double, 4, 2, 40, 1, true, true, false, 64>": "fused FP64 512x512x80, 256x256x80",
+    "k_column_batch_pipe<float, 1, 2, 4, 45, 2>": "timestep 6x8, KH 45",
     "k_column_batch_pipe<float, 1, 2, 4, 40, 2>": "timestep 6x8, KH 40",
+    "k_column_batch_pipe<float, 1, 2, 4, 32, 2>": "timestep 6x8, KH 32",
     "k_hgrad_strip<float, 8, 4>": "timestep 6x8, hgrad",
-    "k_vadv_adjoint<float, 2, 2, 40, false, true>": "reverse FP32 256x256x80",
+    "k_vadv_adjoint<float, 2, 2, 40, false, true, 16>": "reverse FP32 256x256x80",
     "k_hdiff_adjoint_dpp<float, 12, 1>": "reverse FP32 256x256x80",
-    "k_vadv_adjoint<double, 2, 4, 40, false, false>": "reverse FP64 256x256x80",
+    "k_vadv_adjoint<double, 2, 4, 40, false, false, 4>": "reverse FP64 256x256x80",
     "k_hdiff_adjoint_dpp<double, 4, 1>": "reverse FP64 256x256x80",
+    "k_jvp<float, 4, 2, 40, 1, true>": "forward FP32 256x256x80",
+    "k_jvp<double, 2, 2, 40, 1, true>": "forward FP64 256x256x80",
 }
 
 
