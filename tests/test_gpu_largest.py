@@ -1,6 +1,7 @@
-"""The largest problems the fused kernel takes (GPU only): the deepest
-register-held column (96 levels) on a field whose addressed span sits just
-below the 2 GiB that the kernel's 32-bit buffer offsets reach.  Inputs are
+"""The largest problems the buffer-addressed kernels take (GPU only): the
+deepest register-held column (96 levels) on a field whose addressed span sits
+just below the 2 GiB that the kernels' 32-bit buffer offsets reach, for the
+fused kernel, hdiff alone, the reverse pass and the forward mode.  Inputs are
 drawn on the device with a seeded generator, in the distributions of the
 shared input module; column blocks at the corners, in the middle and in the
 ragged last tile are copied back and checked against the FP64 oracle."""
@@ -46,12 +47,14 @@ def largest_nj(ni, es):
     return nj
 
 
-def device_inputs(ni, nj, dtype, seed):
+def device_inputs(ni, nj, dtype, seed, extra=()):
     """u ~ U(-1, 1), coeff ~ U(0, 0.1), wcon ~ U(-1, 1), a, c ~ U(-0.4, 0)
-    with a(0) = c(K-1) = 0, b = 1 + |a| + |c| + U(0, 0.2), on every padded cell."""
+    with a(0) = c(K-1) = 0, b = 1 + |a| + |c| + U(0, 0.2), on every padded cell;
+    each name in `extra` (a loss weight or a tangent) ~ N(0, 1)."""
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
-    f = {n: B.Field.empty(ni, nj, NK, HALO, dtype, fill=0.0) for n in ("u", "coeff", "wcon", "a", "b", "c")}
+    names = ("u", "coeff", "wcon", "a", "b", "c") + tuple(extra)
+    f = {n: B.Field.empty(ni, nj, NK, HALO, dtype, fill=0.0) for n in names}
     f["u"].padded().uniform_(-1.0, 1.0, generator=g)
     f["coeff"].padded().uniform_(0.0, 0.1, generator=g)
     f["wcon"].padded().uniform_(-1.0, 1.0, generator=g)
@@ -62,7 +65,27 @@ def device_inputs(ni, nj, dtype, seed):
     b = f["b"].padded()
     b.uniform_(0.0, 0.2, generator=g)
     b.add_(f["a"].padded().abs()).add_(f["c"].padded().abs()).add_(1.0)
+    for n in extra:
+        f[n].padded().normal_(generator=g)
     return f
+
+
+def edge_shape(dtype):
+    es = 4 if dtype == "f32" else 8
+    ni = 2357 if dtype == "f32" else 1660
+    nj = largest_nj(ni, es)
+    span = span_bytes(ni, nj, NK, es)
+    assert span < SPAN_LIMIT <= span_bytes(ni, nj + 1, NK, es)
+    note("largest field", dtype, (ni, nj, NK), "span %.4f of 2 GiB" % (span / 2.0 ** 31))
+    return ni, nj
+
+
+def block_starts(ni, nj):
+    """Corners, middle, and a block in the ragged last tile in i."""
+    last_i = (ni - 1) // 64 * 64
+    starts = [(0, 0), (ni - BLOCK, nj - BLOCK), (ni // 2, nj // 2), (last_i, nj // 3), (ni - BLOCK, 0),
+              (0, nj - BLOCK)]
+    return [(min(max(i0, 0), ni - BLOCK), min(max(j0, 0), nj - BLOCK)) for i0, j0 in starts]
 
 
 def block(field, i0, j0, w, h, ring):
@@ -75,30 +98,94 @@ def block(field, i0, j0, w, h, ring):
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_fused_on_the_largest_field_its_buffers_address(dtype):
-    es = 4 if dtype == "f32" else 8
-    ni = 2357 if dtype == "f32" else 1660
-    nj = largest_nj(ni, es)
-    span = span_bytes(ni, nj, NK, es)
-    assert span < SPAN_LIMIT <= span_bytes(ni, nj + 1, NK, es)
-    note("largest fused field", dtype, (ni, nj, NK), "span %.4f of 2 GiB" % (span / 2.0 ** 31))
+    ni, nj = edge_shape(dtype)
     f = device_inputs(ni, nj, dtype, SEED + 31)
     x = B.Field.empty(ni, nj, NK, HALO, dtype, fill=-7.0)
     # level 2 runs the fused kernel or refuses: no silent detour to the unfused kernels
     B.stencil_hdiff_vadv(f["u"], f["coeff"], f["wcon"], f["a"], f["b"], f["c"], DT, x, cfg=B.config(level=2))
     torch.cuda.synchronize()
-    last_i = (ni - 1) // 64 * 64  # first column of the ragged last tile in i
-    starts = [(0, 0), (ni - BLOCK, nj - BLOCK), (ni // 2, nj // 2), (last_i, nj // 3), (ni - BLOCK, 0),
-              (0, nj - BLOCK)]
     worst = 0.0
-    for i0, j0 in starts:
-        i0, j0 = min(max(i0, 0), ni - BLOCK), min(max(j0, 0), nj - BLOCK)
+    for i0, j0 in block_starts(ni, nj):
         ins = {n: block(f[n], i0, j0, BLOCK, BLOCK, HALO) for n in f}
         ref = oracle.hdiff_vadv(ins["u"], HALO, ins["coeff"], HALO, ins["wcon"], HALO, ins["a"], HALO,
                                 ins["b"], HALO, ins["c"], HALO, DT)
-        got = block(x, i0, j0, BLOCK, BLOCK, 0)
-        e = normwise(got, ref)
+        e = normwise(block(x, i0, j0, BLOCK, BLOCK, 0), ref)
         worst = max(worst, e)
         assert e <= TOL[dtype], (i0, j0, e)
-    note("  worst normwise %.3e over %d blocks" % (worst, len(starts)))
+    note("  worst normwise %.3e" % worst)
     del f, x
+    torch.cuda.empty_cache()
+
+
+def test_hdiff_on_the_largest_field_its_buffers_address():
+    """The inlined hdiff kernel (level 2: it runs or refuses) in FP32."""
+    ni, nj = edge_shape("f32")
+    f = device_inputs(ni, nj, "f32", SEED + 32)
+    out = B.Field.empty(ni, nj, NK, HALO, "f32", fill=-7.0)
+    B.stencil_hdiff(f["u"], f["coeff"], out, cfg=B.config(level=2))
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i0, j0 in block_starts(ni, nj):
+        ref = oracle.hdiff(block(f["u"], i0, j0, BLOCK, BLOCK, HALO), HALO,
+                           block(f["coeff"], i0, j0, BLOCK, BLOCK, HALO), HALO)
+        e = normwise(block(out, i0, j0, BLOCK, BLOCK, 0), ref)
+        worst = max(worst, e)
+        assert e <= TOL["f32"], (i0, j0, e)
+    note("  worst normwise %.3e" % worst)
+    del f, out
+    torch.cuda.empty_cache()
+
+
+def test_adjoint_on_the_largest_field_its_buffers_address():
+    """Reverse pass in FP64 (whose limiter decisions are the oracle's).  The
+    gradients on a block depend on the loss weights within 2 columns of it and
+    on the inputs within 4 (the limiter decisions of those columns), so the
+    oracle runs on the block grown by 4 columns (clipped at the domain) and
+    the block itself is compared."""
+    ni, nj = edge_shape("f64")
+    f = device_inputs(ni, nj, "f64", SEED + 33, extra=("w",))
+    out = {n: B.Field.empty(ni, nj, NK, HALO, "f64", fill=0.0) for n in ("gu", "gcoeff", "gwcon")}
+    B.stencil_hdiff_vadv_adjoint(f["u"], f["coeff"], f["wcon"], f["a"], f["b"], f["c"], DT, f["w"],
+                                 out["gu"], out["gcoeff"], out["gwcon"])
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i0, j0 in block_starts(ni, nj):
+        si, sj = max(i0 - 4, 0), max(j0 - 4, 0)
+        wi, wj = min(i0 + BLOCK + 4, ni) - si, min(j0 + BLOCK + 4, nj) - sj
+        ins = {n: block(f[n], si, sj, wi, wj, HALO) for n in f}
+        gu, gc, gw = oracle.hdiff_vadv_adjoint(ins["u"], HALO, ins["coeff"], HALO, ins["wcon"], HALO, ins["a"],
+                                               HALO, ins["b"], HALO, ins["c"], HALO, DT,
+                                               ins["w"][:, HALO:-HALO, HALO:-HALO], 0)
+        oi, oj = i0 - si, j0 - sj  # the block inside the grown one
+        pairs = ((block(out["gu"], i0, j0, BLOCK, BLOCK, 0),
+                  gu[:, HALO + oj:HALO + oj + BLOCK, HALO + oi:HALO + oi + BLOCK]),
+                 (block(out["gcoeff"], i0, j0, BLOCK, BLOCK, 0), gc[:, oj:oj + BLOCK, oi:oi + BLOCK]),
+                 (block(out["gwcon"], i0, j0, BLOCK, BLOCK, 0), gw[:, oj:oj + BLOCK, oi:oi + BLOCK]))
+        for got, ref in pairs:
+            e = normwise(got, ref)
+            worst = max(worst, e)
+            assert e <= TOL["f64"], (i0, j0, e)
+    note("  worst normwise %.3e" % worst)
+    del f, out
+    torch.cuda.empty_cache()
+
+
+def test_jvp_on_the_largest_field_its_buffers_address():
+    """Forward mode in FP64 in the direction du: the tangent of a column
+    depends on u and du within 2 columns of it."""
+    ni, nj = edge_shape("f64")
+    f = device_inputs(ni, nj, "f64", SEED + 34, extra=("du",))
+    dx = B.Field.empty(ni, nj, NK, HALO, "f64", fill=-7.0)
+    B.stencil_hdiff_vadv_jvp(f["u"], f["coeff"], f["wcon"], f["a"], f["b"], f["c"], DT, dx, du=f["du"])
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i0, j0 in block_starts(ni, nj):
+        ins = {n: block(f[n], i0, j0, BLOCK, BLOCK, HALO) for n in f}
+        ref = oracle.hdiff_vadv_jvp(ins["u"], HALO, ins["coeff"], HALO, ins["wcon"], HALO, ins["a"], HALO,
+                                    ins["b"], HALO, ins["c"], HALO, DT, du=ins["du"], hdu=HALO)
+        e = normwise(block(dx, i0, j0, BLOCK, BLOCK, 0), ref)
+        worst = max(worst, e)
+        assert e <= TOL["f64"], (i0, j0, e)
+    note("  worst normwise %.3e" % worst)
+    del f, dx
     torch.cuda.empty_cache()
