@@ -1,7 +1,8 @@
 """The largest problems the buffer-addressed kernels take (GPU only): the
 deepest register-held column (96 levels) on a field whose addressed span sits
 just below the 2 GiB that the kernels' 32-bit buffer offsets reach, for the
-fused kernel, hdiff alone, the reverse pass and the forward mode.  Inputs are
+fused kernel, hdiff alone, the reverse pass, the forward mode and the batched
+timestep.  Inputs are
 drawn on the device with a seeded generator, in the distributions of the
 shared input module; column blocks at the corners, in the middle and in the
 ragged last tile are copied back and checked against the FP64 oracle."""
@@ -32,29 +33,30 @@ def note(*a):
     sys.stdout.flush()
 
 
-def span_bytes(ni, nj, nk, es):
-    """Bytes from u's cell (-2, -2, 0) to its last interior cell, for the
+def span_bytes(ni, nj, nk, es, halo=HALO, reach=2):
+    """Bytes a kernel addresses from cell (-reach, -reach, 0) to the last cell
+    its reads reach on the far side (reach - 1 beyond the interior), for the
     layout binding.Field.empty gives (rows padded to 128-byte lines)."""
-    row = -(-(ni + 2 * HALO) // (128 // es)) * (128 // es)
-    plane = row * (nj + 2 * HALO)
-    return ((ni + 3) + (nj + 3) * row + (nk - 1) * plane + 1) * es
+    row = -(-(ni + 2 * halo) // (128 // es)) * (128 // es)
+    plane = row * (nj + 2 * halo)
+    return ((ni + 2 * reach - 1) + (nj + 2 * reach - 1) * row + (nk - 1) * plane + 1) * es
 
 
-def largest_nj(ni, es):
+def largest_nj(ni, es, halo=HALO, reach=2):
     nj = 1
-    while span_bytes(ni, nj + 1, NK, es) < SPAN_LIMIT:
+    while span_bytes(ni, nj + 1, NK, es, halo, reach) < SPAN_LIMIT:
         nj += 1
     return nj
 
 
-def device_inputs(ni, nj, dtype, seed, extra=()):
+def device_inputs(ni, nj, dtype, seed, extra=(), halo=HALO):
     """u ~ U(-1, 1), coeff ~ U(0, 0.1), wcon ~ U(-1, 1), a, c ~ U(-0.4, 0)
     with a(0) = c(K-1) = 0, b = 1 + |a| + |c| + U(0, 0.2), on every padded cell;
     each name in `extra` (a loss weight or a tangent) ~ N(0, 1)."""
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
     names = ("u", "coeff", "wcon", "a", "b", "c") + tuple(extra)
-    f = {n: B.Field.empty(ni, nj, NK, HALO, dtype, fill=0.0) for n in names}
+    f = {n: B.Field.empty(ni, nj, NK, halo, dtype, fill=0.0) for n in names}
     f["u"].padded().uniform_(-1.0, 1.0, generator=g)
     f["coeff"].padded().uniform_(0.0, 0.1, generator=g)
     f["wcon"].padded().uniform_(-1.0, 1.0, generator=g)
@@ -70,12 +72,12 @@ def device_inputs(ni, nj, dtype, seed, extra=()):
     return f
 
 
-def edge_shape(dtype):
+def edge_shape(dtype, halo=HALO, reach=2):
     es = 4 if dtype == "f32" else 8
     ni = 2357 if dtype == "f32" else 1660
-    nj = largest_nj(ni, es)
-    span = span_bytes(ni, nj, NK, es)
-    assert span < SPAN_LIMIT <= span_bytes(ni, nj + 1, NK, es)
+    nj = largest_nj(ni, es, halo, reach)
+    span = span_bytes(ni, nj, NK, es, halo, reach)
+    assert span < SPAN_LIMIT <= span_bytes(ni, nj + 1, NK, es, halo, reach)
     note("largest field", dtype, (ni, nj, NK), "span %.4f of 2 GiB" % (span / 2.0 ** 31))
     return ni, nj
 
@@ -91,8 +93,8 @@ def block_starts(ni, nj):
 def block(field, i0, j0, w, h, ring):
     """Padded float64 copy of interior columns [i0, i0 + w) x [j0, j0 + h)
     with `ring` cells around them."""
-    p = field.padded()
-    return p[:, HALO + j0 - ring:HALO + j0 + h + ring, HALO + i0 - ring:HALO + i0 + w + ring] \
+    p, o = field.padded(), field.hi
+    return p[:, o + j0 - ring:o + j0 + h + ring, o + i0 - ring:o + i0 + w + ring] \
         .detach().to("cpu", torch.float64).numpy().copy()
 
 
@@ -188,4 +190,31 @@ def test_jvp_on_the_largest_field_its_buffers_address():
         assert e <= TOL["f64"], (i0, j0, e)
     note("  worst normwise %.3e" % worst)
     del f, dx
+    torch.cuda.empty_cache()
+
+
+def test_timestep_on_the_largest_subdomain_its_buffers_address():
+    """hdiff -> vadv -> vdiff -> hgrad on one FP32 subdomain whose fields (halo
+    3: hgrad's ring plus hdiff's) span just below 2 GiB from the cell the
+    program kernels address first, (-3, -3, 0).  z on a block depends on u
+    within 3 columns of it."""
+    kappa, bh, bv = 0.1, 0.05, 0.01
+    ni, nj = edge_shape("f32", halo=3, reach=3)
+    f = device_inputs(ni, nj, "f32", SEED + 35, halo=3)
+    z = B.Field.empty(ni, nj, NK, 3, "f32", fill=-7.0)
+    sub = {n: f[n] for n in ("coeff", "wcon", "a", "b", "c")}
+    sub["u"], sub["z"] = [f["u"]], [z]
+    stages = B.STAGE_HDIFF | B.STAGE_VADV | B.STAGE_VDIFF | B.STAGE_HGRAD
+    B.stencil_program_run(B.ProgramSpec([sub], stages=stages, dt=DT, kappa=kappa, beta_h=bh, beta_v=bv))
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i0, j0 in block_starts(ni, nj):
+        ins = {n: block(f[n], i0, j0, BLOCK, BLOCK, 3) for n in f}
+        ref = oracle.timestep(ins["u"], 3, ins["coeff"], 3, ins["wcon"], 3, ins["a"], 3, ins["b"], 3, ins["c"], 3,
+                              DT, kappa, bh, bv)
+        e = normwise(block(z, i0, j0, BLOCK, BLOCK, 0), ref)
+        worst = max(worst, e)
+        assert e <= TOL["f32"], (i0, j0, e)
+    note("  worst normwise %.3e" % worst)
+    del f, z, sub
     torch.cuda.empty_cache()
